@@ -1,0 +1,184 @@
+/*
+ * cn: an MI355X (gfx950) engine for the fixed-step cable equation over many multi-compartment neurons.
+ *
+ * The operation this library performs is the per-time-step computation of CoreNEURON (arXiv 1901.10975):
+ * each cell is a tree of compartments obeying the cable equation (Sec. 2, Eq. 1); every step delivers the synaptic
+ * events that are due, assembles the tree matrix from ionic and synaptic currents, solves it by Gaussian
+ * elimination ordered from the leaves (Hines), updates channel and synapse states, and tests each cell's firing
+ * threshold (Sec. 2, list of per-step operations); spikes reach their targets through NetCons whose delays are at
+ * least one minimum-delay interval, so cells only exchange spikes once per interval (Sec. 2). Mechanism data is
+ * held per type in structure-of-arrays form (Sec. 4.2) and pointers between objects are integer indices (Sec. 3.2).
+ *
+ * Units (Sec. 2, Eq. 1): mV, ms, um, um^2, MOhm, uF/cm^2, S/cm^2, nA, uS.
+ *
+ * Conventions for every entry point:
+ *   - every function returns a status code (CN_OK or an error); no C++ exception crosses this boundary and nothing
+ *     aborts; cn_last_error() gives a message for the calling thread's last failure;
+ *   - all array arguments are HOST pointers; they are borrowed for the duration of the call only (the library
+ *     deep-copies what it keeps); output buffers are owned by the caller;
+ *   - a model is not thread-safe; different models may be used from different threads;
+ *   - device memory belongs to the model (allocated through cn_options.dev_alloc when given, else hipMalloc) and is
+ *     released by cn_model_destroy.
+ */
+#ifndef CN_H
+#define CN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CN_OK 0
+#define CN_E_INVALID 1  /* bad argument or model description */
+#define CN_E_NOMEM 2    /* host or device allocation failed */
+#define CN_E_DEVICE 3   /* a HIP call failed (message kept in cn_last_error) */
+#define CN_E_STATE 4    /* call not allowed in the model's current state (e.g. a second dt) */
+#define CN_E_CAPACITY 5 /* an event or spike buffer overflowed; results of that run are not valid */
+#define CN_E_NUMERIC 6  /* a non-finite membrane potential was found */
+
+/* mechanism types. Density mechanisms (HH, PAS, KM, CAHI) have at most one instance per compartment; point
+ * processes (EXPSYN, ICLAMP) may have many. Parameter columns, in order:
+ *   CN_MECH_HH:     gnabar, gkbar, gl (S/cm^2), el (mV)      Hodgkin-Huxley Na/K/leak, ena 50 mV, ek -77 mV
+ *   CN_MECH_PAS:    g (S/cm^2), e (mV)                        passive leak
+ *   CN_MECH_KM:     gbar (S/cm^2)                             slow non-inactivating K (tau near 80-100 ms)
+ *   CN_MECH_CAHI:   gbar (S/cm^2)                             high-threshold Ca, eca 120 mV, shell calcium decay
+ *   CN_MECH_EXPSYN: tau (ms), e (mV)                          conductance synapse g(t) decaying with tau
+ *   CN_MECH_ICLAMP: del (ms), dur (ms), amp (nA)              current clamp on for t in [del, del + dur)
+ * The rate equations and integration rule of each type are stated in the repository's design notes. */
+enum {
+  CN_MECH_HH = 0,
+  CN_MECH_PAS = 1,
+  CN_MECH_KM = 2,
+  CN_MECH_CAHI = 3,
+  CN_MECH_EXPSYN = 4,
+  CN_MECH_ICLAMP = 5,
+  CN_MECH_COUNT = 6
+};
+
+enum { CN_PREC_FP64 = 0, CN_PREC_FP32_MECH = 1 };
+enum { CN_LAYOUT_AUTO = 0, CN_LAYOUT_LEVEL = 1 };
+
+/* Cell morphology (Sec. 2: each cell is a tree of compartments). Cells own contiguous compartment ranges
+ * [cell_offset[c], cell_offset[c+1]); parent[] is cell-local with -1 at the root (local 0) and parent[i] < i. */
+typedef struct cn_topology {
+  int32_t n_cells;
+  int64_t n_comp;
+  const int64_t *cell_offset; /* [n_cells + 1], cell_offset[0] = 0, strictly increasing */
+  const int32_t *parent;      /* [n_comp] */
+  const double *area;         /* [n_comp] membrane area, um^2, > 0 */
+  const double *ri;           /* [n_comp] axial resistance to the parent, MOhm, > 0 (ignored at roots) */
+  const double *cm;           /* [n_comp] specific capacitance, uF/cm^2, > 0 */
+  double v_init;              /* initial membrane potential, mV */
+  double celsius;             /* temperature for the HH q10 factor, degC */
+} cn_topology;
+
+/* One instance table per mechanism type (Sec. 4.2: instances grouped by type, properties as separate arrays).
+ * node[k] is the global compartment of instance k; node == NULL means dense: n == n_comp and instance k sits at
+ * compartment k. param[j] is an [n] array or NULL, in which case every instance takes param_scalar[j]. */
+typedef struct cn_mech_table {
+  int32_t type;
+  int64_t n;
+  const int64_t *node;
+  const double *param[4];
+  double param_scalar[4];
+} cn_mech_table;
+
+/* Network: NetCons from a cell's threshold detector to an ExpSyn instance (Sec. 3.2 NetCon; Sec. 2 spike
+ * delivery), external events ("kicks") and per-synapse background streams (Sec. 3.5, Random123). ExpSyn instances
+ * are numbered in the order of the EXPSYN table. */
+typedef struct cn_network {
+  int64_t n_netcon;
+  const int32_t *src_cell;   /* [n_netcon] */
+  const int64_t *target_syn; /* [n_netcon] */
+  const double *weight;      /* [n_netcon] uS, added to the target's g on delivery */
+  const double *delay;       /* [n_netcon] ms; delivered floor(delay/dt + 0.5) >= 1 steps after the spike */
+  const double *threshold;   /* [n_cells] mV, or NULL for threshold_scalar */
+  double threshold_scalar;
+  int64_t n_kick;            /* external events: g[kick_syn] += kick_weight at the start of step kick_step */
+  const int64_t *kick_step;
+  const int64_t *kick_syn;
+  const double *kick_weight;
+  double poisson_rate_hz;        /* background rate per synapse (0: none) */
+  const double *poisson_weight;  /* [n_syn] uS, or NULL when poisson_rate_hz is 0 */
+  uint64_t seed;                 /* key of the counter-based background streams */
+  const int64_t *poisson_key;    /* [n_syn] stream id of each synapse (>= 0), or NULL: the instance index */
+} cn_network;
+
+/* Allocation callbacks let a host framework own device memory (e.g. PyTorch's caching allocator). dev_alloc
+ * returns a device pointer of at least `bytes` bytes aligned to 256 bytes, or NULL; dev_free releases it. */
+typedef void *(*cn_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*cn_free_fn)(void *ptr, void *ctx);
+
+typedef struct cn_options {
+  int32_t precision;      /* CN_PREC_FP64 or CN_PREC_FP32_MECH (FP32 mechanism states and rates; voltage,
+                             matrix assembly and the tree solve stay FP64) */
+  int32_t layout;         /* CN_LAYOUT_AUTO or CN_LAYOUT_LEVEL */
+  void *stream;           /* hipStream_t for all device work, or NULL for the default stream */
+  cn_alloc_fn dev_alloc;  /* optional */
+  cn_free_fn dev_free;    /* required when dev_alloc is given */
+  void *alloc_ctx;
+  int32_t event_capacity; /* events per cell group per interval (0: default 1024) */
+  int32_t max_interval;   /* upper bound on steps per interval (0: default 64) */
+  int32_t group_threads;  /* threads per cell group (0: auto) */
+  int32_t use_graph;      /* 1: replay one captured hipGraph per interval; 0: direct launches */
+  int32_t timing;         /* 1: time the interval kernel with HIP events (see cn_stats) */
+  int32_t validate_only;  /* 1: build and check the device layout on the host only, touching no device; the model
+                             then answers cn_model_info and nothing else (cn_run returns CN_E_STATE) */
+  int32_t reserved[6];
+} cn_options;
+
+typedef struct cn_model cn_model;
+
+/* Build a model: validate, order and pack cells for the device, upload. On CN_OK *out receives a handle owned by
+ * the library (free with cn_model_destroy). Errors: CN_E_INVALID (bad topology: parent order, non-positive or
+ * non-finite area/ri/cm, index out of range, duplicate density instance, unknown type, NaN parameter, ...),
+ * CN_E_NOMEM, CN_E_DEVICE. The time step is not fixed here: see cn_run. */
+int cn_model_create(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
+                    const cn_options *opt, cn_model **out);
+
+/* Advance the simulation from its current step to step N = llround(tstop / dt) (tstop is absolute simulated time,
+ * t = n * dt exactly; time is an integer step count, never accumulated). The first call fixes dt; a later call
+ * with a different dt returns CN_E_STATE, and so does tstop below the current time. Work is queued on the model's
+ * stream and the call returns after it completes. Errors: CN_E_CAPACITY (event queue overflow), CN_E_NUMERIC
+ * (non-finite voltage, checked at interval ends), CN_E_DEVICE. */
+int cn_run(cn_model *m, double tstop, double dt);
+
+/* Spikes recorded so far, sorted by (step, gid): cell index, step index (the spike happened during the step
+ * ending at that index) and the linearly interpolated crossing time in ms. With gid == NULL only *n_out is set.
+ * Otherwise cap must be >= the count (else CN_E_INVALID); any of step/t_interp may be NULL. */
+int cn_spikes(const cn_model *m, int64_t *n_out, int32_t *gid, int64_t *step, double *t_interp, int64_t cap);
+
+/* Membrane potential of every compartment at the current step, in the caller's compartment order (FP64 in both
+ * precision modes). n_comp must equal the model's count (else CN_E_INVALID). */
+int cn_voltages(const cn_model *m, double *v_out, int64_t n_comp);
+
+/* A mechanism state at the current step in the caller's instance order, as double. type/which select:
+ * HH 0:m 1:h 2:n; KM 0:n; CAHI 0:m 1:cai; EXPSYN 0:g. n must equal the instance count (else CN_E_INVALID). */
+int cn_mech_state(const cn_model *m, int32_t type, int32_t which, double *out, int64_t n);
+
+/* Model facts for reporting. */
+typedef struct cn_info {
+  int64_t n_comp, n_syn, n_netcon, n_groups, step, device_bytes;
+  int32_t n_cells, interval_steps, group_threads, group_slots, max_group_nodes, max_levels, ring_slots,
+      event_capacity, precision, lds_bytes;
+  double dt;
+} cn_info;
+int cn_model_info(const cn_model *m, cn_info *out);
+
+/* With cn_options.timing set: total milliseconds and launch count of the interval kernel over all cn_run calls,
+ * from HIP events recorded on the model's stream around each launch. */
+int cn_stats(const cn_model *m, double *kernel_ms, int64_t *kernel_launches);
+
+/* Free everything the model owns. NULL is a no-op. */
+void cn_model_destroy(cn_model *m);
+
+/* Message describing the calling thread's last non-OK status. */
+const char *cn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -34,7 +34,7 @@ class OrcSpec(C.Structure):
         ("n_nc", C.c_int64), ("nc_src", _i32p), ("nc_syn", _i64p), ("nc_w", _dp), ("nc_delay", _dp),
         ("threshold", _dp),
         ("n_kick", C.c_int64), ("kick_step", _i64p), ("kick_syn", _i64p), ("kick_w", _dp),
-        ("poisson_rate_hz", C.c_double), ("poisson_w", _dp), ("seed", C.c_uint64),
+        ("poisson_rate_hz", C.c_double), ("poisson_w", _dp), ("poisson_key", _i64p), ("seed", C.c_uint64),
         ("dt", C.c_double), ("batch_steps", C.c_int32), ("n_threads", C.c_int32), ("keep_matrix", C.c_int32),
     ]
 
@@ -143,6 +143,8 @@ class OracleSim:
         s.poisson_rate_hz = model.poisson_rate_hz
         pw = model.poisson_weight if model.poisson_weight.shape[0] else np.zeros(model.n_syn)
         s.poisson_w = _p(arr(pw, np.float64), C.c_double)
+        pk = model.poisson_key if getattr(model, "poisson_key", None) is not None else np.arange(model.n_syn)
+        s.poisson_key = _p(arr(pk, np.int64), C.c_int64)
         s.seed = int(model.seed) & 0xFFFFFFFFFFFFFFFF
         s.dt = dt
         s.batch_steps = int(batch_steps)

@@ -35,9 +35,9 @@
  *      index, then the background event.
  *   R8 threshold: a spike at step n+1 iff v_root(n) < theta <= v_root(n+1); reported time is the linear
  *      interpolation of the crossing within the step.
- *   R9 background: an event for synapse s at step n iff R(seed, s, n) < floor(p 2^32), p = rate dt 1e-3, where
- *      R(seed, s, n) is word (n mod 4) of Philox4x32-10 with key (seed low, seed high) and counter
- *      (s low, s high, n/4 low, n/4 high). Its weight is that synapse's background weight.
+ *   R9 background: an event for synapse s at step n iff R(seed, k_s, n) < floor(p 2^32), p = rate dt 1e-3, where
+ *      k_s is the synapse's stream id and R(seed, k, n) is word (n mod 4) of Philox4x32-10 with key (seed low,
+ *      seed high) and counter (k low, k high, n/4 low, n/4 high). Its weight is that synapse's background weight.
  *   R10 IClamp: on for steps n with ceil(del/dt - 0.5) <= n < ceil((del+dur)/dt - 0.5).
  *   R11 ExpSyn: g decays as g exp(-dt/tau) after the solve; i = g (v - e) nA.
  */
@@ -190,7 +190,7 @@ struct orc_model {
   int64_t n_nc; int64_t *nc_syn; double *nc_w; int64_t *nc_D; int64_t *out_off, *out_nc;
   double *theta;
   int64_t n_kick; int64_t *kick_step, *kick_syn; double *kick_w; int64_t kick_pos;
-  double rate; double *pw; uint64_t seed; uint64_t bg_thresh;
+  double rate; double *pw; int64_t *pkey; uint64_t seed; uint64_t bg_thresh;
   int64_t Q; ivec *ring; int32_t M;
   ivec pend_gid, pend_step;
   /* run state */
@@ -250,7 +250,7 @@ void orc_destroy(orc_model *m) {
                   m->km_n, m->km_c.off, m->km_c.idx, m->cahi_node, m->ca_g, m->ca_m, m->ca_cai, m->cahi_c.off,
                   m->cahi_c.idx, m->syn_node, m->syn_e, m->syn_f, m->syn_g, m->syn_c.off, m->syn_c.idx,
                   m->icl_node, m->icl_amp, m->icl_on, m->icl_off, m->icl_c.off, m->icl_c.idx, m->nc_syn, m->nc_w,
-                  m->nc_D, m->out_off, m->out_nc, m->theta, m->kick_step, m->kick_syn, m->kick_w, m->pw,
+                  m->nc_D, m->out_off, m->out_nc, m->theta, m->kick_step, m->kick_syn, m->kick_w, m->pw, m->pkey,
                   m->pend_gid.v, m->pend_step.v, m->sp_gid.v, m->sp_step.v, m->sp_t, m->spiked, m->spike_t};
   for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
   if (m->ring) {
@@ -433,6 +433,9 @@ orc_model *orc_create(const orc_spec *s) {
   m->seed = s->seed;
   if (m->rate > 0.0) {
     DUP(m->pw, s->poisson_w, s->n_syn, double);
+    DUP(m->pkey, s->poisson_key, s->n_syn, int64_t);
+    for (int64_t k = 0; k < s->n_syn; ++k)
+      if (m->pkey[k] < 0) { set_err("negative background stream id"); goto fail; }
     double p = m->rate * s->dt * 1e-3;
     double t = floor(p * 4294967296.0);
     m->bg_thresh = t >= 4294967296.0 ? (uint64_t)4294967296ULL : (uint64_t)t;
@@ -472,7 +475,7 @@ static int deliver(orc_model *m, int64_t n) {
     int64_t cnt = 0;
 #pragma omp parallel for num_threads(m->n_threads) reduction(+ : cnt) schedule(static)
     for (int64_t sy = 0; sy < m->n_syn; ++sy) {
-      if ((uint64_t)orc_poisson_draw(m->seed, (uint64_t)sy, (uint64_t)n) < m->bg_thresh) {
+      if ((uint64_t)orc_poisson_draw(m->seed, (uint64_t)m->pkey[sy], (uint64_t)n) < m->bg_thresh) {
         m->syn_g[sy] += m->pw[sy];
         cnt++;
       }

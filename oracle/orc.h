@@ -50,6 +50,7 @@ typedef struct orc_spec {
   const double *threshold; /* [n_cells] mV */
   int64_t n_kick; const int64_t *kick_step, *kick_syn; const double *kick_w;
   double poisson_rate_hz; const double *poisson_w; /* [n_syn] */
+  const int64_t *poisson_key; /* [n_syn] stream id of each synapse */
   uint64_t seed;
   double dt;
   int32_t batch_steps; /* 0: spikes fan out at once; M > 0: spikes fan out at the end of each M-step interval */

@@ -1,0 +1,1152 @@
+// Host side of the cn library: the C-ABI of include/cn.h, validation, the device layout (cell groups, level
+// order, structure-of-arrays tables) and the interval driver.
+//
+// Model setup follows the paper's memory-setup phase (Sec. 3.1, Sec. 3.2, Sec. 4.2): mechanism instances grouped
+// by type in structure-of-arrays columns, integer indices instead of pointers, and a node permutation for the
+// device (Sec. 4.4). The driver runs the fixed-step loop in chunks of at most one minimum-delay interval
+// (Sec. 2: spikes are exchanged once per minimum delay), one kernel launch per chunk, optionally replayed from a
+// captured hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "cn.h"
+#include "cn_internal.h"
+
+namespace cn {
+hipError_t launch_interval(const KParams &p, bool fp32, int threads, int slots, int lds_bytes, hipStream_t st);
+hipError_t set_interval_lds(bool fp32, int threads, int slots, int lds_bytes);
+hipError_t launch_advance(int64_t *ctl, int32_t M, hipStream_t st);
+hipError_t launch_set_ctl(int64_t *ctl, int64_t n_begin, int64_t n_target, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *ptr, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_read_state(const KParams &p, bool fp32, int64_t n_nodes, int64_t step, int type, int which,
+                             double *out, hipStream_t st);
+}  // namespace cn
+
+using namespace cn;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+struct Err {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess)                                                                              \
+      throw Err{CN_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)};                      \
+  } while (0)
+
+const int N_PARAMS[CN_MECH_COUNT] = {4, 2, 1, 1, 2, 3};
+const char *MECH_NAME[CN_MECH_COUNT] = {"hh", "pas", "km", "cahi", "expsyn", "iclamp"};
+
+// one parameter column of a mechanism table, expanded
+struct Col {
+  std::vector<double> v;
+  bool uniform = true;
+  double s = 0.0;
+};
+
+struct Table {
+  bool present = false;
+  int64_t n = 0;
+  std::vector<int64_t> node;  // per instance
+  Col p[4];
+};
+
+// Hodgkin-Huxley steady states at v (initial states), same kinetics as the device code, in double
+void hh_inf(double v, double &m, double &h, double &n) {
+  auto vtrap = [](double x, double y) { return std::fabs(x / y) < 1e-6 ? y * (1.0 - x / y / 2.0) : x / (std::exp(x / y) - 1.0); };
+  const double am = 0.1 * vtrap(-(v + 40.0), 10.0), bm = 4.0 * std::exp(-(v + 65.0) / 18.0);
+  const double ah = 0.07 * std::exp(-(v + 65.0) / 20.0), bh = 1.0 / (std::exp(-(v + 35.0) / 10.0) + 1.0);
+  const double an = 0.01 * vtrap(-(v + 55.0), 10.0), bn = 0.125 * std::exp(-(v + 65.0) / 80.0);
+  m = am / (am + bm);
+  h = ah / (ah + bh);
+  n = an / (an + bn);
+}
+double km_inf(double v) { return 1.0 / (1.0 + std::exp(-(v + 35.0) / 10.0)); }
+double cahi_inf(double v) { return 1.0 / (1.0 + std::exp(-(v + 20.0) / 9.0)); }
+
+}  // namespace
+
+struct cn_model {
+  // ---- caller's description (kept for dt-dependent setup and readouts)
+  int32_t n_cells = 0;
+  int64_t n_comp = 0;
+  std::vector<int64_t> cell_off;
+  std::vector<int32_t> parent;
+  std::vector<double> area, ri, cm;
+  double v_init = -65.0, celsius = 6.3;
+  Table mech[CN_MECH_COUNT];
+  int64_t n_syn = 0, n_nc = 0, n_kick = 0;
+  std::vector<int32_t> nc_src;
+  std::vector<int64_t> nc_syn;
+  std::vector<double> nc_w, nc_delay, theta;
+  std::vector<int64_t> kick_step, kick_syn;
+  std::vector<double> kick_w;
+  double rate = 0.0;
+  std::vector<double> pw;
+  std::vector<int64_t> pkey;
+  uint64_t seed = 0;
+  cn_options opt{};
+  bool fp32 = false;
+
+  // ---- layout
+  int threads = 256, slots = 4, nmax = 1024;
+  int64_t n_groups = 0;
+  std::vector<GroupDesc> groups;
+  std::vector<int32_t> lvl_start;
+  std::vector<int64_t> dev_of_node, node_of_dev;  // caller compartment <-> device node
+  std::vector<int64_t> dev_of_syn, syn_of_dev;    // caller ExpSyn <-> device synapse
+  std::vector<int64_t> icl_of_dev;                // device IClamp -> caller instance
+  std::vector<int32_t> cell_of_devcell;           // device cell slot -> caller cell
+  std::vector<double> host_b;                     // b per device node (for the dt-dependent diagonal term)
+  int32_t max_levels = 0, max_group_syn = 0, max_group_nodes = 0;
+
+  // ---- device
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<void *> allocs;
+  int64_t device_bytes = 0;
+  KParams kp{};
+  int lds_bytes = 0;
+  int32_t spk_total = 0;
+  int32_t drain_every = 1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+
+  // ---- run state
+  bool dt_fixed = false, broken = false;
+  double dt = 0.0;
+  int64_t step = 0;
+  std::vector<int32_t> sp_gid;
+  std::vector<int64_t> sp_step;
+  std::vector<double> sp_t;
+  std::vector<hipEvent_t> ev_pool;
+  double kernel_ms = 0.0;
+  int64_t kernel_launches = 0;
+
+  bool dry = false;  // validate_only: no device work
+
+  void *dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    device_bytes += (int64_t)bytes;
+    if (dry) return nullptr;
+    void *p = nullptr;
+    if (opt.dev_alloc) {
+      p = opt.dev_alloc(bytes, opt.alloc_ctx);
+      if (!p) throw Err{CN_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) throw Err{CN_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    }
+    allocs.push_back(p);
+    return p;
+  }
+  template <typename T>
+  T *upload(const std::vector<T> &h) {
+    T *d = static_cast<T *>(dalloc(h.size() * sizeof(T)));
+    if (!h.empty() && !dry) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, stream));
+    return d;
+  }
+  // upload as double or as float (FP32-mechanism path)
+  void *upload_s(const std::vector<double> &h) {
+    if (!fp32) return upload(h);
+    std::vector<float> f(h.begin(), h.end());
+    return upload(f);
+  }
+  ~cn_model() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (stream && !dry) (void)hipStreamSynchronize(stream);
+    for (void *p : allocs) {
+      if (opt.dev_alloc) opt.dev_free(p, opt.alloc_ctx);
+      else (void)hipFree(p);
+    }
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+bool finite_all(const double *p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+void read_tables(cn_model *m, const cn_mech_table *mechs, int32_t n_mechs) {
+  if (n_mechs < 0 || (n_mechs > 0 && !mechs)) throw Err{CN_E_INVALID, "bad mechanism table list"};
+  for (int32_t k = 0; k < n_mechs; ++k) {
+    const cn_mech_table &mt = mechs[k];
+    if (mt.type < 0 || mt.type >= CN_MECH_COUNT) throw Err{CN_E_INVALID, "unknown mechanism type " + std::to_string(mt.type)};
+    Table &t = m->mech[mt.type];
+    const char *nm = MECH_NAME[mt.type];
+    if (t.present) throw Err{CN_E_INVALID, std::string("two tables of type ") + nm};
+    t.present = true;
+    if (mt.n < 0) throw Err{CN_E_INVALID, std::string(nm) + ": negative count"};
+    if (!mt.node && mt.n != m->n_comp)
+      throw Err{CN_E_INVALID, std::string(nm) + ": dense table needs n == n_comp"};
+    t.n = mt.n;
+    t.node.resize(mt.n);
+    for (int64_t i = 0; i < mt.n; ++i) {
+      t.node[i] = mt.node ? mt.node[i] : i;
+      if (t.node[i] < 0 || t.node[i] >= m->n_comp)
+        throw Err{CN_E_INVALID, std::string(nm) + ": instance " + std::to_string(i) + " node out of range"};
+    }
+    if (mt.type <= CN_MECH_CAHI) {
+      std::vector<char> seen(m->n_comp, 0);
+      for (int64_t i = 0; i < mt.n; ++i) {
+        if (seen[t.node[i]]) throw Err{CN_E_INVALID, std::string(nm) + ": two instances at one compartment"};
+        seen[t.node[i]] = 1;
+      }
+    }
+    for (int j = 0; j < N_PARAMS[mt.type]; ++j) {
+      Col &c = t.p[j];
+      if (mt.param[j]) {
+        c.v.assign(mt.param[j], mt.param[j] + mt.n);
+        if (!finite_all(c.v.data(), mt.n)) throw Err{CN_E_INVALID, std::string(nm) + ": non-finite parameter"};
+        c.uniform = std::all_of(c.v.begin(), c.v.end(), [&](double x) { return x == c.v[0]; });
+        c.s = mt.n ? c.v[0] : 0.0;
+      } else {
+        if (!std::isfinite(mt.param_scalar[j])) throw Err{CN_E_INVALID, std::string(nm) + ": non-finite parameter"};
+        c.v.assign(mt.n, mt.param_scalar[j]);
+        c.uniform = true;
+        c.s = mt.param_scalar[j];
+      }
+    }
+  }
+  const Table &syn = m->mech[CN_MECH_EXPSYN];
+  for (int64_t i = 0; i < syn.n; ++i)
+    if (!(syn.p[0].v[i] > 0.0)) throw Err{CN_E_INVALID, "expsyn: tau must be positive"};
+  m->n_syn = syn.n;
+}
+
+void read_network(cn_model *m, const cn_network *net) {
+  m->theta.assign(m->n_cells, 0.0);
+  if (!net) return;
+  if (net->n_netcon < 0 || net->n_netcon >= (int64_t)0x7FFFFFFF) throw Err{CN_E_INVALID, "bad NetCon count"};
+  if (net->n_kick < 0 || net->n_kick >= (int64_t)0x7FFFFFFF) throw Err{CN_E_INVALID, "bad kick count"};
+  m->n_nc = net->n_netcon;
+  if (m->n_nc > 0 && (!net->src_cell || !net->target_syn || !net->weight || !net->delay))
+    throw Err{CN_E_INVALID, "NetCon arrays missing"};
+  m->nc_src.assign(net->src_cell, net->src_cell + m->n_nc);
+  m->nc_syn.assign(net->target_syn, net->target_syn + m->n_nc);
+  m->nc_w.assign(net->weight, net->weight + m->n_nc);
+  m->nc_delay.assign(net->delay, net->delay + m->n_nc);
+  for (int64_t k = 0; k < m->n_nc; ++k) {
+    if (m->nc_src[k] < 0 || m->nc_src[k] >= m->n_cells) throw Err{CN_E_INVALID, "NetCon source out of range"};
+    if (m->nc_syn[k] < 0 || m->nc_syn[k] >= m->n_syn) throw Err{CN_E_INVALID, "NetCon target out of range"};
+    if (!std::isfinite(m->nc_w[k]) || !std::isfinite(m->nc_delay[k]) || !(m->nc_delay[k] > 0.0))
+      throw Err{CN_E_INVALID, "NetCon weight/delay must be finite, delay > 0"};
+  }
+  if (net->threshold) m->theta.assign(net->threshold, net->threshold + m->n_cells);
+  else m->theta.assign(m->n_cells, net->threshold_scalar);
+  if (!finite_all(m->theta.data(), m->n_cells)) throw Err{CN_E_INVALID, "non-finite threshold"};
+  m->n_kick = net->n_kick;
+  if (m->n_kick > 0 && (!net->kick_step || !net->kick_syn || !net->kick_weight))
+    throw Err{CN_E_INVALID, "kick arrays missing"};
+  m->kick_step.assign(net->kick_step, net->kick_step + m->n_kick);
+  m->kick_syn.assign(net->kick_syn, net->kick_syn + m->n_kick);
+  m->kick_w.assign(net->kick_weight, net->kick_weight + m->n_kick);
+  for (int64_t k = 0; k < m->n_kick; ++k)
+    if (m->kick_step[k] < 0 || m->kick_syn[k] < 0 || m->kick_syn[k] >= m->n_syn || !std::isfinite(m->kick_w[k]))
+      throw Err{CN_E_INVALID, "bad kick"};
+  m->rate = net->poisson_rate_hz;
+  if (!std::isfinite(m->rate) || m->rate < 0.0) throw Err{CN_E_INVALID, "bad background rate"};
+  if (m->rate > 0.0) {
+    if (!net->poisson_weight) throw Err{CN_E_INVALID, "background weights missing"};
+    m->pw.assign(net->poisson_weight, net->poisson_weight + m->n_syn);
+    if (!finite_all(m->pw.data(), m->n_syn)) throw Err{CN_E_INVALID, "non-finite background weight"};
+  }
+  m->pkey.resize(m->n_syn);
+  for (int64_t k = 0; k < m->n_syn; ++k) {
+    m->pkey[k] = net->poisson_key ? net->poisson_key[k] : k;
+    if (m->pkey[k] < 0) throw Err{CN_E_INVALID, "negative background stream id"};
+  }
+  m->seed = net->seed;
+}
+
+// ---- device layout: cell groups (bin packing), level order, tables
+void build_layout(cn_model *m) {
+  const int64_t N = m->n_comp;
+  std::vector<int32_t> depth(N, 0), cell_levels(m->n_cells, 0), cell_size(m->n_cells);
+  std::vector<int64_t> syn_per_cell(m->n_cells, 0);
+  std::vector<int32_t> cell_of(N);
+  int32_t max_cell = 0;
+  for (int32_t c = 0; c < m->n_cells; ++c) {
+    const int64_t i0 = m->cell_off[c], n = m->cell_off[c + 1] - i0;
+    cell_size[c] = (int32_t)n;
+    max_cell = std::max<int32_t>(max_cell, (int32_t)n);
+    int32_t lv = 0;
+    for (int64_t k = 0; k < n; ++k) {
+      cell_of[i0 + k] = c;
+      depth[i0 + k] = k == 0 ? 0 : depth[i0 + m->parent[i0 + k]] + 1;
+      lv = std::max(lv, depth[i0 + k] + 1);
+    }
+    cell_levels[c] = lv;
+  }
+  const Table &syn = m->mech[CN_MECH_EXPSYN];
+  for (int64_t k = 0; k < syn.n; ++k) syn_per_cell[cell_of[syn.node[k]]]++;
+
+  // group shape: T threads x K register slots, capacity T*K nodes
+  int T = m->opt.group_threads > 0 ? m->opt.group_threads : 256;
+  if (T != 128 && T != 256 && T != 512) throw Err{CN_E_INVALID, "group_threads must be 128, 256 or 512"};
+  const int kmax = T == 512 ? 4 : 8;
+  int K = 1;
+  while (K < kmax && T * K < max_cell) K *= 2;
+  if (T * K < max_cell) throw Err{CN_E_INVALID, "a cell has more compartments (" + std::to_string(max_cell) +
+                                                   ") than one cell group holds (" + std::to_string(T * K) + ")"};
+  if (K < 4 && N >= (int64_t)T * 4 * 512) K = 4;  // large models: fuller groups
+  m->threads = T;
+  m->slots = K;
+  m->nmax = T * K;
+  const int64_t syn_cap = 4096;
+
+  // best-fit decreasing on compartments, with a synapse cap per group
+  std::vector<int32_t> order(m->n_cells);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cell_size[a] > cell_size[b]; });
+  std::vector<std::vector<int32_t>> gcells;
+  std::vector<int64_t> gnodes, gsyn;
+  std::multimap<int64_t, int32_t> room;  // remaining capacity -> group
+  for (int32_t c : order) {
+    const int64_t sz = cell_size[c], sy = syn_per_cell[c];
+    if (sy >= MAX_GROUP_SYN) throw Err{CN_E_INVALID, "too many synapses on one cell"};
+    int32_t g = -1;
+    int tries = 0;
+    for (auto it = room.lower_bound(sz); it != room.end() && tries < 8; ++it, ++tries) {
+      if (gsyn[it->second] + sy <= syn_cap) {
+        g = it->second;
+        room.erase(it);
+        break;
+      }
+    }
+    if (g < 0) {
+      g = (int32_t)gcells.size();
+      gcells.emplace_back();
+      gnodes.push_back(0);
+      gsyn.push_back(0);
+    }
+    gcells[g].push_back(c);
+    gnodes[g] += sz;
+    gsyn[g] += sy;
+    const int64_t rem = m->nmax - gnodes[g];
+    if (rem > 0) room.emplace(rem, g);
+  }
+  // heaviest groups first
+  std::vector<int32_t> gorder(gcells.size());
+  std::iota(gorder.begin(), gorder.end(), 0);
+  std::stable_sort(gorder.begin(), gorder.end(), [&](int32_t a, int32_t b) { return gnodes[a] > gnodes[b]; });
+
+  m->n_groups = (int64_t)gcells.size();
+  m->groups.assign(m->n_groups, GroupDesc{});
+  m->dev_of_node.assign(N, -1);
+  m->node_of_dev.assign(N, -1);
+  m->cell_of_devcell.clear();
+  m->lvl_start.clear();
+  int64_t node_base = 0;
+  int32_t cell_base = 0;
+  // children lists per caller compartment, ascending local index
+  std::vector<int64_t> ch_off(N + 1, 0), ch_list(N, 0);
+  for (int64_t i = 0; i < N; ++i) {
+    const int32_t c = cell_of[i];
+    const int64_t loc = i - m->cell_off[c];
+    if (loc > 0) ch_off[m->cell_off[c] + m->parent[i] + 1]++;
+  }
+  for (int64_t i = 0; i < N; ++i) ch_off[i + 1] += ch_off[i];
+  {
+    std::vector<int64_t> fill(N, 0);
+    for (int64_t i = 0; i < N; ++i) {
+      const int32_t c = cell_of[i];
+      const int64_t loc = i - m->cell_off[c];
+      if (loc > 0) {
+        const int64_t p = m->cell_off[c] + m->parent[i];
+        ch_list[ch_off[p] + fill[p]++] = i;
+      }
+    }
+  }
+  std::vector<int64_t> lvl_nodes, next;
+  m->max_levels = 0;
+  m->max_group_nodes = 0;
+  for (int64_t gi = 0; gi < m->n_groups; ++gi) {
+    const int32_t g = gorder[gi];
+    GroupDesc &gd = m->groups[gi];
+    gd.node_base = node_base;
+    gd.n_cells = (int32_t)gcells[g].size();
+    gd.cell_base = cell_base;
+    gd.lvl_base = (int32_t)m->lvl_start.size();
+    int64_t pos = 0;
+    lvl_nodes.clear();
+    for (int32_t c : gcells[g]) {
+      lvl_nodes.push_back(m->cell_off[c]);
+      m->cell_of_devcell.push_back(c);
+    }
+    int32_t levels = 0;
+    while (!lvl_nodes.empty()) {
+      m->lvl_start.push_back((int32_t)pos);
+      next.clear();
+      for (int64_t i : lvl_nodes) {
+        m->dev_of_node[i] = node_base + pos;
+        m->node_of_dev[node_base + pos] = i;
+        ++pos;
+        for (int64_t q = ch_off[i]; q < ch_off[i + 1]; ++q) next.push_back(ch_list[q]);
+      }
+      lvl_nodes.swap(next);
+      ++levels;
+    }
+    m->lvl_start.push_back((int32_t)pos);
+    gd.n_levels = levels;
+    gd.n_nodes = (int32_t)pos;
+    m->max_levels = std::max(m->max_levels, levels);
+    m->max_group_nodes = std::max<int32_t>(m->max_group_nodes, (int32_t)pos);
+    node_base += pos;
+    cell_base += gd.n_cells;
+  }
+}
+
+}  // namespace
+
+// ---- invariants the interval kernel relies on for every index it forms (checked on the host before upload)
+static void layout_fail(const char *what) { throw Err{CN_E_INVALID, std::string("internal layout check failed: ") + what}; }
+
+static void check_tree_layout(const cn_model *m, const std::vector<int32_t> &par, const std::vector<uint32_t> &ch) {
+  int64_t total = 0;
+  for (int64_t g = 0; g < m->n_groups; ++g) {
+    const GroupDesc &gd = m->groups[g];
+    if (gd.node_base != total) layout_fail("node base");
+    if (gd.n_nodes < 1 || gd.n_nodes > m->nmax || gd.n_cells < 1) layout_fail("group size");
+    if (gd.n_levels < 1 || gd.lvl_base < 0 || gd.lvl_base + gd.n_levels >= (int64_t)m->lvl_start.size())
+      layout_fail("level table");
+    const int32_t *lv = m->lvl_start.data() + gd.lvl_base;
+    if (lv[0] != 0 || lv[gd.n_levels] != gd.n_nodes || lv[1] != gd.n_cells) layout_fail("level bounds");
+    for (int L = 0; L < gd.n_levels; ++L)
+      if (lv[L + 1] <= lv[L]) layout_fail("empty level");
+    int64_t n_children = 0;
+    for (int L = 0; L < gd.n_levels; ++L) {
+      for (int32_t q = lv[L]; q < lv[L + 1]; ++q) {
+        const int64_t i = gd.node_base + q;
+        const int32_t pq = par[i];
+        if (L == 0 ? pq != -1 : (pq < lv[L - 1] || pq >= lv[L])) layout_fail("parent level");
+        const int32_t c0 = (int32_t)(ch[i] & 0xFFFFu), cn = (int32_t)(ch[i] >> 16);
+        if (cn > 0) {
+          if (L + 1 >= gd.n_levels || c0 < lv[L + 1] || c0 + cn > lv[L + 2]) layout_fail("children range");
+          for (int32_t c = c0; c < c0 + cn; ++c)
+            if (par[gd.node_base + c] != q) layout_fail("child's parent");
+        }
+        n_children += cn;
+      }
+    }
+    if (n_children != gd.n_nodes - gd.n_cells) layout_fail("child count");
+    total += gd.n_nodes;
+  }
+  if (total != m->n_comp) layout_fail("node total");
+}
+
+static void check_ranges(const cn_model *m, const std::vector<int2> &r, bool syn) {
+  int64_t covered_total = 0;
+  for (int64_t g = 0; g < m->n_groups; ++g) {
+    const GroupDesc &gd = m->groups[g];
+    int64_t next = 0;
+    for (int32_t q = 0; q < gd.n_nodes; ++q) {
+      const int2 x = r[gd.node_base + q];
+      if (x.y < 0) layout_fail("instance range");
+      if (x.y == 0) continue;
+      if (x.x != next) layout_fail("instance ranges do not tile");
+      next += x.y;
+    }
+    if (syn && next != gd.n_syn) layout_fail("synapse count");
+    covered_total += next;
+  }
+  const int64_t want = syn ? m->mech[CN_MECH_EXPSYN].n : m->mech[CN_MECH_ICLAMP].n;
+  if (covered_total != want) layout_fail("instance total");
+}
+
+// ---- tables that do not depend on dt
+static void build_tables(cn_model *m) {
+  const int64_t N = m->n_comp;
+  const bool f32 = m->fp32;
+  std::vector<double> a(N), b(N), sa(N);
+  std::vector<int32_t> par(N);
+  std::vector<uint32_t> ch(N);
+  std::vector<uint8_t> mf(N, 0);
+  // group of each device node, and group-local index
+  std::vector<int32_t> grp_of_dev(N);
+  for (int64_t g = 0; g < m->n_groups; ++g)
+    for (int32_t q = 0; q < m->groups[g].n_nodes; ++q) grp_of_dev[m->groups[g].node_base + q] = (int32_t)g;
+  std::vector<int32_t> first_child(N, -1), n_child(N, 0);
+  for (int64_t dn = 0; dn < N; ++dn) {
+    const int64_t i = m->node_of_dev[dn];
+    const GroupDesc &gd = m->groups[grp_of_dev[dn]];
+    // caller cell of i
+    const int64_t c = std::upper_bound(m->cell_off.begin(), m->cell_off.end(), i) - m->cell_off.begin() - 1;
+    const int64_t loc = i - m->cell_off[c];
+    sa[dn] = 100.0 / m->area[i];
+    if (loc == 0) {
+      a[dn] = b[dn] = 0.0;
+      par[dn] = -1;
+    } else {
+      const int64_t pi = m->cell_off[c] + m->parent[i];
+      const double g = 1.0 / m->ri[i];
+      a[dn] = -100.0 * g / m->area[pi];
+      b[dn] = -100.0 * g / m->area[i];
+      const int64_t pd = m->dev_of_node[pi];
+      par[dn] = (int32_t)(pd - gd.node_base);
+      const int32_t ql = (int32_t)(dn - gd.node_base);
+      if (first_child[pd] < 0 || ql < first_child[pd]) first_child[pd] = ql;
+      n_child[pd]++;
+    }
+  }
+  for (int64_t dn = 0; dn < N; ++dn)
+    ch[dn] = (uint32_t)(first_child[dn] < 0 ? 0 : first_child[dn]) | ((uint32_t)n_child[dn] << 16);
+  check_tree_layout(m, par, ch);
+
+  // density mechanisms: flags, per-node parameters when not uniform, initial states at v_init
+  std::vector<double> st[6];
+  for (auto &s : st) s.assign(N, 0.0);
+  double hm, hh, hn;
+  hh_inf(m->v_init, hm, hh, hn);
+  const int flag_of[4] = {MF_HH, MF_PAS, MF_KM, MF_CAHI};
+  std::vector<double> prm[4][4];
+  for (int t = 0; t < 4; ++t) {
+    const Table &tb = m->mech[t];
+    if (!tb.present) continue;
+    for (int j = 0; j < N_PARAMS[t]; ++j)
+      if (!tb.p[j].uniform) prm[t][j].assign(N, 0.0);
+    for (int64_t k = 0; k < tb.n; ++k) {
+      const int64_t dn = m->dev_of_node[tb.node[k]];
+      mf[dn] |= (uint8_t)flag_of[t];
+      for (int j = 0; j < N_PARAMS[t]; ++j)
+        if (!tb.p[j].uniform) prm[t][j][dn] = tb.p[j].v[k];
+      if (t == CN_MECH_HH) {
+        st[0][dn] = hm;
+        st[1][dn] = hh;
+        st[2][dn] = hn;
+      } else if (t == CN_MECH_KM) {
+        st[3][dn] = km_inf(m->v_init);
+      } else if (t == CN_MECH_CAHI) {
+        st[4][dn] = cahi_inf(m->v_init);
+        st[5][dn] = 5e-5;
+      }
+    }
+  }
+  KParams &p = m->kp;
+  m->host_b = b;
+  p.nd_a = m->upload(a);
+  p.nd_b = m->upload(b);
+  p.nd_sa = m->upload(sa);
+  p.nd_par = m->upload(par);
+  p.nd_ch = m->upload(ch);
+  p.nd_mf = m->upload(mf);
+  p.v = m->upload(std::vector<double>(N, m->v_init));
+  for (int k = 0; k < 6; ++k) p.st[k] = m->upload_s(st[k]);
+  auto col = [&](int t, int j, const double **arr, double *sc) {
+    const Table &tb = m->mech[t];
+    *arr = nullptr;
+    *sc = tb.present ? tb.p[j].s : 0.0;
+    if (tb.present && !tb.p[j].uniform) *arr = m->upload(prm[t][j]);
+  };
+  col(CN_MECH_HH, 0, &p.hh_gna, &p.hh_gna_s);
+  col(CN_MECH_HH, 1, &p.hh_gk, &p.hh_gk_s);
+  col(CN_MECH_HH, 2, &p.hh_gl, &p.hh_gl_s);
+  col(CN_MECH_HH, 3, &p.hh_el, &p.hh_el_s);
+  // the kernel reads all four hh columns from arrays when any one is not uniform
+  if (p.hh_gna || p.hh_gk || p.hh_gl || p.hh_el) {
+    const Table &tb = m->mech[CN_MECH_HH];
+    const double **arrs[4] = {&p.hh_gna, &p.hh_gk, &p.hh_gl, &p.hh_el};
+    for (int j = 0; j < 4; ++j)
+      if (!*arrs[j]) {
+        std::vector<double> v(N, 0.0);
+        for (int64_t k = 0; k < tb.n; ++k) v[m->dev_of_node[tb.node[k]]] = tb.p[j].v[k];
+        *arrs[j] = m->upload(v);
+      }
+  }
+  col(CN_MECH_PAS, 0, &p.pas_g, &p.pas_g_s);
+  col(CN_MECH_PAS, 1, &p.pas_e, &p.pas_e_s);
+  if (p.pas_g || p.pas_e) {
+    const Table &tb = m->mech[CN_MECH_PAS];
+    const double **arrs[2] = {&p.pas_g, &p.pas_e};
+    for (int j = 0; j < 2; ++j)
+      if (!*arrs[j]) {
+        std::vector<double> v(N, 0.0);
+        for (int64_t k = 0; k < tb.n; ++k) v[m->dev_of_node[tb.node[k]]] = tb.p[j].v[k];
+        *arrs[j] = m->upload(v);
+      }
+  }
+  col(CN_MECH_KM, 0, &p.km_g, &p.km_g_s);
+  col(CN_MECH_CAHI, 0, &p.ca_g, &p.ca_g_s);
+
+  // point processes in device order: per node, instances in ascending caller index
+  auto order_pp = [&](const Table &tb, std::vector<int64_t> &of_dev, std::vector<int64_t> *dev_of) {
+    std::vector<int64_t> idx(tb.n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+      return m->dev_of_node[tb.node[x]] < m->dev_of_node[tb.node[y]];
+    });
+    of_dev = idx;
+    if (dev_of) {
+      dev_of->assign(tb.n, 0);
+      for (int64_t d = 0; d < tb.n; ++d) (*dev_of)[idx[d]] = d;
+    }
+  };
+  const Table &syn = m->mech[CN_MECH_EXPSYN];
+  order_pp(syn, m->syn_of_dev, &m->dev_of_syn);
+  const Table &icl = m->mech[CN_MECH_ICLAMP];
+  order_pp(icl, m->icl_of_dev, nullptr);
+  std::vector<int2> nd_syn(N, int2{0, 0}), nd_icl(N, int2{0, 0});
+  // group bases and per-node ranges
+  {
+    int64_t sd = 0, id = 0;
+    for (int64_t g = 0; g < m->n_groups; ++g) {
+      GroupDesc &gd = m->groups[g];
+      gd.syn_base = sd;
+      gd.icl_base = (int32_t)id;
+      const int64_t end = gd.node_base + gd.n_nodes;
+      const int64_t s0 = sd, i0 = id;
+      while (sd < syn.n && m->dev_of_node[syn.node[m->syn_of_dev[sd]]] < end) {
+        const int64_t dn = m->dev_of_node[syn.node[m->syn_of_dev[sd]]];
+        if (nd_syn[dn].y == 0) nd_syn[dn].x = (int)(sd - s0);
+        nd_syn[dn].y++;
+        ++sd;
+      }
+      while (id < icl.n && m->dev_of_node[icl.node[m->icl_of_dev[id]]] < end) {
+        const int64_t dn = m->dev_of_node[icl.node[m->icl_of_dev[id]]];
+        if (nd_icl[dn].y == 0) nd_icl[dn].x = (int)(id - i0);
+        nd_icl[dn].y++;
+        ++id;
+      }
+      gd.n_syn = (int32_t)(sd - s0);
+      m->max_group_syn = std::max(m->max_group_syn, gd.n_syn);
+    }
+  }
+  check_ranges(m, nd_syn, true);
+  check_ranges(m, nd_icl, false);
+  p.nd_syn = m->upload(nd_syn);
+  p.nd_icl = m->upload(nd_icl);
+  {
+    std::vector<double> g0(syn.n, 0.0), e(syn.n), wbg(syn.n, 0.0);
+    std::vector<int64_t> sid(syn.n);
+    for (int64_t d = 0; d < syn.n; ++d) {
+      const int64_t k = m->syn_of_dev[d];
+      e[d] = syn.p[1].v[k];
+      sid[d] = m->pkey.empty() ? k : m->pkey[k];
+      if (m->rate > 0.0) wbg[d] = m->pw[k];
+    }
+    p.syn_g = m->upload_s(g0);
+    p.syn_e_s = syn.n ? syn.p[1].s : 0.0;
+    p.syn_e = (syn.n && !syn.p[1].uniform) ? m->upload(e) : nullptr;
+    p.syn_id = m->upload(sid);
+    p.syn_wbg = m->upload_s(wbg);
+  }
+  // cells in device order
+  {
+    std::vector<int32_t> gid(m->n_cells);
+    std::vector<double> th(m->n_cells);
+    for (int32_t c = 0; c < m->n_cells; ++c) {
+      gid[c] = m->cell_of_devcell[c];
+      th[c] = m->theta[m->cell_of_devcell[c]];
+    }
+    p.cell_gid = m->upload(gid);
+    p.cell_theta = m->upload(th);
+  }
+  // network: targets, source CSR; kicks by (group, step, id)
+  {
+    std::vector<int32_t> tgt_g(m->n_nc), tgt_l(m->n_nc);
+    std::vector<int32_t> grp_of_dsyn(syn.n);
+    for (int64_t g = 0; g < m->n_groups; ++g)
+      for (int32_t s = 0; s < m->groups[g].n_syn; ++s) grp_of_dsyn[m->groups[g].syn_base + s] = (int32_t)g;
+    for (int64_t k = 0; k < m->n_nc; ++k) {
+      const int64_t d = m->dev_of_syn[m->nc_syn[k]];
+      tgt_g[k] = grp_of_dsyn[d];
+      tgt_l[k] = (int32_t)(d - m->groups[tgt_g[k]].syn_base);
+    }
+    p.nc_tgt_group = m->upload(tgt_g);
+    p.nc_tgt_lsyn = m->upload(tgt_l);
+    p.nc_w = m->upload_s(m->nc_w);
+    std::vector<int64_t> off(m->n_cells + 1, 0);
+    for (int64_t k = 0; k < m->n_nc; ++k) off[m->nc_src[k] + 1]++;
+    for (int32_t c = 0; c < m->n_cells; ++c) off[c + 1] += off[c];
+    std::vector<int32_t> onc(m->n_nc);
+    std::vector<int64_t> fill(m->n_cells, 0);
+    for (int64_t k = 0; k < m->n_nc; ++k) onc[off[m->nc_src[k]] + fill[m->nc_src[k]]++] = (int32_t)k;
+    p.out_off = m->upload(off);
+    p.out_nc = m->upload(onc);
+    std::vector<int64_t> kidx(m->n_kick);
+    std::iota(kidx.begin(), kidx.end(), 0);
+    std::vector<int32_t> kg(m->n_kick);
+    for (int64_t k = 0; k < m->n_kick; ++k) kg[k] = grp_of_dsyn[m->dev_of_syn[m->kick_syn[k]]];
+    std::stable_sort(kidx.begin(), kidx.end(), [&](int64_t x, int64_t y) {
+      if (kg[x] != kg[y]) return kg[x] < kg[y];
+      return m->kick_step[x] < m->kick_step[y];
+    });
+    std::vector<int64_t> ks(m->n_kick);
+    std::vector<int32_t> kl(m->n_kick), kid(m->n_kick);
+    for (auto &gd : m->groups) gd.kick_base = gd.n_kick = 0;
+    for (int64_t q = 0; q < m->n_kick; ++q) {
+      const int64_t k = kidx[q];
+      ks[q] = m->kick_step[k];
+      const int64_t d = m->dev_of_syn[m->kick_syn[k]];
+      kl[q] = (int32_t)(d - m->groups[kg[k]].syn_base);
+      kid[q] = (int32_t)k;
+    }
+    for (int64_t q = m->n_kick - 1; q >= 0; --q) {
+      GroupDesc &gd = m->groups[kg[kidx[q]]];
+      gd.kick_base = (int32_t)q;
+      gd.n_kick++;
+    }
+    for (int64_t k = 0; k < m->n_nc; ++k)
+      if (tgt_g[k] < 0 || tgt_g[k] >= m->n_groups || tgt_l[k] < 0 || tgt_l[k] >= m->groups[tgt_g[k]].n_syn)
+        throw Err{CN_E_INVALID, "internal layout check failed: NetCon target"};
+    for (int64_t g = 0; g < m->n_groups; ++g) {
+      const GroupDesc &gd = m->groups[g];
+      if (gd.kick_base < 0 || gd.n_kick < 0 || gd.kick_base + gd.n_kick > m->n_kick)
+        throw Err{CN_E_INVALID, "internal layout check failed: kick range"};
+      for (int32_t q = gd.kick_base; q < gd.kick_base + gd.n_kick; ++q)
+        if (kl[q] < 0 || kl[q] >= gd.n_syn || (q > gd.kick_base && ks[q] < ks[q - 1]))
+          throw Err{CN_E_INVALID, "internal layout check failed: kick order"};
+    }
+    p.kick_step = m->upload(ks);
+    p.kick_lsyn = m->upload(kl);
+    p.kick_id = m->upload(kid);
+    p.kick_w = m->upload_s(m->kick_w);
+  }
+  p.lvl_start = m->upload(m->lvl_start);
+  p.n_groups = (int32_t)m->n_groups;
+}
+
+// ---- tables that depend on dt; allocation of the event ring and spike buffers; graph capture
+static void prepare_dt(cn_model *m, double dt) {
+  KParams &p = m->kp;
+  const int64_t N = m->n_comp;
+  p.dt = dt;
+  p.q10dt = std::pow(3.0, (m->celsius - 6.3) / 10.0) * dt;
+  p.ca_fm = 1.0 - std::exp(-dt / 1.0);
+  p.ca_fr = 1.0 - std::exp(-dt / 80.0);
+  p.ca_k = 1e4 / (2.0 * 96485.33212 * 0.1) * 80.0;
+  {
+    std::vector<double> k(N);
+    // capacitance term 1e-3 cm/dt (S/cm^2) and the node's own axial coupling -b
+    for (int64_t dn = 0; dn < N; ++dn) k[dn] = 1e-3 * m->cm[m->node_of_dev[dn]] / dt - m->host_b[dn];
+    p.nd_k = m->upload(k);
+  }
+  const Table &syn = m->mech[CN_MECH_EXPSYN];
+  {
+    std::vector<double> f(syn.n);
+    bool uni = true;
+    for (int64_t d = 0; d < syn.n; ++d) {
+      f[d] = std::exp(-dt / syn.p[0].v[m->syn_of_dev[d]]);
+      if (f[d] != f[0]) uni = false;
+    }
+    p.syn_f_s = syn.n ? f[0] : 0.0;
+    p.syn_f = (syn.n && !uni) ? m->upload_s(f) : nullptr;
+  }
+  const Table &icl = m->mech[CN_MECH_ICLAMP];
+  {
+    std::vector<double> cur(icl.n);
+    std::vector<int64_t> on(icl.n), off(icl.n);
+    for (int64_t d = 0; d < icl.n; ++d) {
+      const int64_t k = m->icl_of_dev[d];
+      cur[d] = 100.0 * icl.p[2].v[k] / m->area[icl.node[k]];
+      on[d] = (int64_t)std::ceil(icl.p[0].v[k] / dt - 0.5);
+      off[d] = (int64_t)std::ceil((icl.p[0].v[k] + icl.p[1].v[k]) / dt - 0.5);
+    }
+    p.icl_cur = m->upload(cur);
+    p.icl_on = m->upload(on);
+    p.icl_off = m->upload(off);
+  }
+  // delays in steps, interval length M, ring of interval slots
+  int64_t minD = INT64_MAX, maxD = 0;
+  std::vector<int32_t> D(m->n_nc);
+  for (int64_t k = 0; k < m->n_nc; ++k) {
+    const double x = std::floor(m->nc_delay[k] / dt + 0.5);
+    if (!(x >= 1.0) || x > 1e9) throw Err{CN_E_INVALID, "NetCon delay must be at least one step"};
+    D[k] = (int32_t)x;
+    minD = std::min<int64_t>(minD, D[k]);
+    maxD = std::max<int64_t>(maxD, D[k]);
+  }
+  int64_t M = m->opt.max_interval > 0 ? m->opt.max_interval : 64;
+  if (M > MAX_INTERVAL) M = MAX_INTERVAL;
+  if (m->n_nc > 0) M = std::min(M, minD);
+  p.M = (int32_t)M;
+  p.ring = (int32_t)(2 + maxD / M);
+  p.nc_D = m->upload(D);
+  // background stream threshold: event iff word < floor(p 2^32), p = rate dt 1e-3
+  p.has_bg = m->rate > 0.0 ? 1 : 0;
+  {
+    const double pr = m->rate * dt * 1e-3;
+    const double t = std::floor(pr * 4294967296.0);
+    p.bg_thresh = t >= 4294967296.0 ? 4294967296ull : (uint64_t)t;
+  }
+  p.seed = m->seed;
+  // event ring
+  int cap = m->opt.event_capacity > 0 ? m->opt.event_capacity : 1024;
+  int pc = 1;
+  while (pc < cap) pc <<= 1;
+  p.ev_cap = pc;
+  const int64_t nbk = (int64_t)p.ring * m->n_groups;
+  p.ev_cnt = static_cast<int32_t *>(m->dalloc(nbk * sizeof(int32_t)));
+  HIPCHK(launch_fill_i32(p.ev_cnt, nbk, 0, m->stream));
+  p.ev_key = static_cast<uint64_t *>(m->dalloc(nbk * (int64_t)pc * sizeof(uint64_t)));
+  // per-group spike scratch: at most ceil(M/2) spikes per cell per chunk
+  const int32_t per_cell = (int32_t)((M + 1) / 2);
+  int64_t sb = 0;
+  for (auto &gd : m->groups) {
+    gd.spk_base = (int32_t)sb;
+    sb += (int64_t)gd.n_cells * per_cell;
+  }
+  if (sb >= INT32_MAX) throw Err{CN_E_INVALID, "model too large for the spike scratch"};
+  p.gsp_pack = static_cast<int32_t *>(m->dalloc(sb * sizeof(int32_t)));
+  p.gsp_frac = static_cast<double *>(m->dalloc(sb * sizeof(double)));
+  // spike record drained to the host every drain_every chunks
+  const int64_t per_chunk = (int64_t)m->n_cells * per_cell;
+  int64_t de = std::max<int64_t>(1, std::min<int64_t>(64, (16ll << 20) / std::max<int64_t>(1, per_chunk)));
+  m->drain_every = (int32_t)de;
+  const int64_t rc = per_chunk * de;
+  if (rc >= INT32_MAX) throw Err{CN_E_INVALID, "model too large for the spike record"};
+  p.rec_cap = (int32_t)rc;
+  p.rec_cnt = static_cast<int32_t *>(m->dalloc(sizeof(int32_t) * 4));
+  p.flags = static_cast<int32_t *>(m->dalloc(sizeof(int32_t) * 4));
+  HIPCHK(launch_fill_i32(p.rec_cnt, 4, 0, m->stream));
+  HIPCHK(launch_fill_i32(p.flags, 4, 0, m->stream));
+  p.rec_gid = static_cast<int32_t *>(m->dalloc(rc * sizeof(int32_t)));
+  p.rec_step = static_cast<int64_t *>(m->dalloc(rc * sizeof(int64_t)));
+  p.rec_t = static_cast<double *>(m->dalloc(rc * sizeof(double)));
+  p.ctl = static_cast<int64_t *>(m->dalloc(4 * sizeof(int64_t)));
+  p.groups = m->upload(m->groups);
+  // LDS: v, s1, s2 (doubles), synaptic g, event keys, step segments, counters
+  const int ssz = m->fp32 ? 4 : 8;
+  p.smax = std::max<int32_t>(8, (m->max_group_syn + 7) / 8 * 8);
+  int off = 24 * m->nmax;
+  p.lds_syn_off = off;
+  off += p.smax * ssz;
+  off = (off + 15) / 16 * 16;
+  p.lds_ev_off = off;
+  off += p.ev_cap * 8;
+  p.lds_seg_off = off;
+  off += (p.M + 1) * 4;
+  off = (off + 15) / 16 * 16;
+  p.lds_misc_off = off;
+  off += 16;
+  m->lds_bytes = off;
+  if (m->lds_bytes > 160 * 1024)
+    throw Err{CN_E_INVALID, "cell groups need " + std::to_string(m->lds_bytes) + " bytes of LDS (event_capacity "
+                                "or synapses per group too large)"};
+  HIPCHK(set_interval_lds(m->fp32, m->threads, m->slots, m->lds_bytes));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  if (m->opt.use_graph) {
+    HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = launch_interval(m->kp, m->fp32, m->threads, m->slots, m->lds_bytes, m->stream);
+    hipError_t e2 = launch_advance(p.ctl, p.M, m->stream);
+    hipError_t e3 = hipStreamEndCapture(m->stream, &m->graph);
+    HIPCHK(e1);
+    HIPCHK(e2);
+    HIPCHK(e3);
+    HIPCHK(hipGraphInstantiate(&m->gexec, m->graph, nullptr, nullptr, 0));
+  }
+}
+
+static void drain(cn_model *m, int32_t n_timed) {
+  KParams &p = m->kp;
+  HIPCHK(hipStreamSynchronize(m->stream));
+  int32_t cnt = 0, flags[4];
+  HIPCHK(hipMemcpy(&cnt, p.rec_cnt, sizeof cnt, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(flags, p.flags, sizeof flags, hipMemcpyDeviceToHost));
+  const int32_t got = std::min(cnt, p.rec_cap);
+  if (got > 0) {
+    const size_t b = m->sp_gid.size();
+    m->sp_gid.resize(b + got);
+    m->sp_step.resize(b + got);
+    m->sp_t.resize(b + got);
+    HIPCHK(hipMemcpy(m->sp_gid.data() + b, p.rec_gid, got * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(m->sp_step.data() + b, p.rec_step, got * sizeof(int64_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(m->sp_t.data() + b, p.rec_t, got * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  HIPCHK(launch_fill_i32(p.rec_cnt, 1, 0, m->stream));
+  for (int32_t k = 0; k < n_timed; ++k) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, m->ev_pool[2 * k], m->ev_pool[2 * k + 1]));
+    m->kernel_ms += ms;
+    m->kernel_launches++;
+  }
+  if (flags[FLAG_EV_OVERFLOW] || flags[FLAG_REC_OVERFLOW]) {
+    m->broken = true;
+    throw Err{CN_E_CAPACITY, flags[FLAG_EV_OVERFLOW] ? "event ring overflow: raise cn_options.event_capacity"
+                                                     : "spike record overflow"};
+  }
+  if (flags[FLAG_NONFINITE]) {
+    m->broken = true;
+    throw Err{CN_E_NUMERIC, "non-finite membrane potential"};
+  }
+}
+
+extern "C" {
+
+const char *cn_last_error(void) { return g_err.c_str(); }
+
+int cn_model_create(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
+                    const cn_options *opt, cn_model **out) {
+  if (!out) return fail(CN_E_INVALID, "out is NULL");
+  *out = nullptr;
+  cn_model *m = nullptr;
+  try {
+    m = new cn_model();
+  } catch (...) {
+    return fail(CN_E_NOMEM, "out of host memory");
+  }
+  try {
+    if (!topo) throw Err{CN_E_INVALID, "topology is NULL"};
+    if (opt) m->opt = *opt;
+    if (m->opt.precision != CN_PREC_FP64 && m->opt.precision != CN_PREC_FP32_MECH)
+      throw Err{CN_E_INVALID, "unknown precision"};
+    if (m->opt.layout != CN_LAYOUT_AUTO && m->opt.layout != CN_LAYOUT_LEVEL) throw Err{CN_E_INVALID, "unknown layout"};
+    if (m->opt.dev_alloc && !m->opt.dev_free) throw Err{CN_E_INVALID, "dev_alloc without dev_free"};
+    m->fp32 = m->opt.precision == CN_PREC_FP32_MECH;
+    if (topo->n_cells <= 0 || topo->n_comp <= 0) throw Err{CN_E_INVALID, "empty model"};
+    if (!topo->cell_offset || !topo->parent || !topo->area || !topo->ri || !topo->cm)
+      throw Err{CN_E_INVALID, "topology arrays missing"};
+    if (!std::isfinite(topo->v_init) || !std::isfinite(topo->celsius)) throw Err{CN_E_INVALID, "non-finite v_init/celsius"};
+    m->n_cells = topo->n_cells;
+    m->n_comp = topo->n_comp;
+    m->cell_off.assign(topo->cell_offset, topo->cell_offset + m->n_cells + 1);
+    if (m->cell_off[0] != 0 || m->cell_off[m->n_cells] != m->n_comp) throw Err{CN_E_INVALID, "bad cell_offset"};
+    for (int32_t c = 0; c < m->n_cells; ++c)
+      if (m->cell_off[c + 1] <= m->cell_off[c]) throw Err{CN_E_INVALID, "cell_offset must be strictly increasing"};
+    m->parent.assign(topo->parent, topo->parent + m->n_comp);
+    m->area.assign(topo->area, topo->area + m->n_comp);
+    m->ri.assign(topo->ri, topo->ri + m->n_comp);
+    m->cm.assign(topo->cm, topo->cm + m->n_comp);
+    for (int32_t c = 0; c < m->n_cells; ++c) {
+      const int64_t i0 = m->cell_off[c], n = m->cell_off[c + 1] - i0;
+      for (int64_t k = 0; k < n; ++k) {
+        const int64_t i = i0 + k;
+        const int32_t pp = m->parent[i];
+        if (!(m->area[i] > 0.0) || !std::isfinite(m->area[i]) || !(m->cm[i] > 0.0) || !std::isfinite(m->cm[i]))
+          throw Err{CN_E_INVALID, "area and cm must be positive and finite (compartment " + std::to_string(i) + ")"};
+        if (k == 0) {
+          if (pp != -1) throw Err{CN_E_INVALID, "root parent must be -1 (cell " + std::to_string(c) + ")"};
+        } else {
+          if (pp < 0 || pp >= k) throw Err{CN_E_INVALID, "parent[i] must lie in [0, i) (compartment " + std::to_string(i) + ")"};
+          if (!(m->ri[i] > 0.0) || !std::isfinite(m->ri[i]))
+            throw Err{CN_E_INVALID, "ri must be positive and finite (compartment " + std::to_string(i) + ")"};
+        }
+      }
+    }
+    m->v_init = topo->v_init;
+    m->celsius = topo->celsius;
+    read_tables(m, mechs, n_mechs);
+    read_network(m, net);
+    m->dry = m->opt.validate_only != 0;
+    if (m->dry) {
+      m->stream = nullptr;
+    } else if (m->opt.stream) {
+      m->stream = static_cast<hipStream_t>(m->opt.stream);
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking));
+      m->own_stream = true;
+    }
+    build_layout(m);
+    build_tables(m);
+    if (!m->dry) HIPCHK(hipStreamSynchronize(m->stream));
+  } catch (const Err &e) {
+    delete m;
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc &) {
+    delete m;
+    return fail(CN_E_NOMEM, "out of host memory");
+  } catch (...) {
+    delete m;
+    return fail(CN_E_INVALID, "unexpected failure in cn_model_create");
+  }
+  *out = m;
+  return CN_OK;
+}
+
+int cn_run(cn_model *m, double tstop, double dt) {
+  if (!m) return fail(CN_E_INVALID, "model is NULL");
+  if (m->broken) return fail(CN_E_STATE, "model is in an error state after a failed run");
+  if (m->dry) return fail(CN_E_STATE, "model was built with validate_only");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(tstop)) return fail(CN_E_INVALID, "bad tstop or dt");
+  try {
+    if (!m->dt_fixed) {
+      prepare_dt(m, dt);
+      m->dt = dt;
+      m->dt_fixed = true;
+    } else if (dt != m->dt) {
+      return fail(CN_E_STATE, "dt differs from the first cn_run call");
+    }
+    const int64_t N = llround(tstop / dt);
+    if (N < m->step) return fail(CN_E_STATE, "tstop lies before the current time");
+    if (N == m->step) return CN_OK;
+    KParams &p = m->kp;
+    HIPCHK(launch_set_ctl(p.ctl, m->step, N, m->stream));
+    const bool timing = m->opt.timing != 0;
+    if (timing && (int32_t)m->ev_pool.size() < 2 * m->drain_every) {
+      while ((int32_t)m->ev_pool.size() < 2 * m->drain_every) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        m->ev_pool.push_back(e);
+      }
+    }
+    int64_t cur = m->step;
+    int32_t since = 0;
+    while (cur < N) {
+      if (timing) HIPCHK(hipEventRecord(m->ev_pool[2 * since], m->stream));
+      if (m->gexec) {
+        HIPCHK(hipGraphLaunch(m->gexec, m->stream));
+      } else {
+        HIPCHK(launch_interval(p, m->fp32, m->threads, m->slots, m->lds_bytes, m->stream));
+        HIPCHK(launch_advance(p.ctl, p.M, m->stream));
+      }
+      if (timing) HIPCHK(hipEventRecord(m->ev_pool[2 * since + 1], m->stream));
+      cur = std::min<int64_t>(N, (cur / p.M + 1) * p.M);
+      ++since;
+      if (since == m->drain_every || cur == N) {
+        drain(m, timing ? since : 0);
+        since = 0;
+      }
+    }
+    m->step = N;
+  } catch (const Err &e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc &) {
+    return fail(CN_E_NOMEM, "out of host memory");
+  } catch (...) {
+    return fail(CN_E_DEVICE, "unexpected failure in cn_run");
+  }
+  return CN_OK;
+}
+
+int cn_spikes(const cn_model *m, int64_t *n_out, int32_t *gid, int64_t *step, double *t_interp, int64_t cap) {
+  if (!m || !n_out) return fail(CN_E_INVALID, "NULL argument");
+  const int64_t n = (int64_t)m->sp_gid.size();
+  *n_out = n;
+  if (!gid) return CN_OK;
+  if (cap < n) return fail(CN_E_INVALID, "spike buffer too small");
+  std::vector<int64_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    if (m->sp_step[a] != m->sp_step[b]) return m->sp_step[a] < m->sp_step[b];
+    return m->sp_gid[a] < m->sp_gid[b];
+  });
+  for (int64_t k = 0; k < n; ++k) {
+    gid[k] = m->sp_gid[idx[k]];
+    if (step) step[k] = m->sp_step[idx[k]];
+    if (t_interp) t_interp[k] = m->sp_t[idx[k]];
+  }
+  return CN_OK;
+}
+
+int cn_voltages(const cn_model *m, double *v_out, int64_t n_comp) {
+  if (!m || !v_out) return fail(CN_E_INVALID, "NULL argument");
+  if (m->dry) return fail(CN_E_STATE, "model was built with validate_only");
+  if (n_comp != m->n_comp) return fail(CN_E_INVALID, "n_comp does not match the model");
+  try {
+    std::vector<double> dv(m->n_comp);
+    HIPCHK(hipStreamSynchronize(m->stream));
+    HIPCHK(hipMemcpy(dv.data(), m->kp.v, m->n_comp * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m->n_comp; ++i) v_out[i] = dv[m->dev_of_node[i]];
+  } catch (const Err &e) {
+    return fail(e.code, e.msg);
+  }
+  return CN_OK;
+}
+
+int cn_mech_state(const cn_model *m, int32_t type, int32_t which, double *out, int64_t n) {
+  if (!m || !out) return fail(CN_E_INVALID, "NULL argument");
+  if (m->dry) return fail(CN_E_STATE, "model was built with validate_only");
+  if (type < 0 || type >= CN_MECH_COUNT || !m->mech[type].present) return fail(CN_E_INVALID, "no such mechanism");
+  const Table &tb = m->mech[type];
+  if (n != tb.n) return fail(CN_E_INVALID, "n does not match the instance count");
+  const int nw[CN_MECH_COUNT] = {3, 0, 1, 2, 1, 0};
+  if (which < 0 || which >= nw[type]) return fail(CN_E_INVALID, "no such state");
+  try {
+    HIPCHK(hipStreamSynchronize(m->stream));
+    if (type == CN_MECH_EXPSYN) {
+      std::vector<double> g(tb.n);
+      if (m->fp32) {
+        std::vector<float> f(tb.n);
+        HIPCHK(hipMemcpy(f.data(), m->kp.syn_g, tb.n * sizeof(float), hipMemcpyDeviceToHost));
+        for (int64_t d = 0; d < tb.n; ++d) g[d] = f[d];
+      } else {
+        HIPCHK(hipMemcpy(g.data(), m->kp.syn_g, tb.n * sizeof(double), hipMemcpyDeviceToHost));
+      }
+      for (int64_t k = 0; k < tb.n; ++k) out[k] = g[m->dev_of_syn[k]];
+      return CN_OK;
+    }
+    if (!m->dt_fixed) {  // before the first run states sit at their initial values
+      double hm, hh, hn;
+      hh_inf(m->v_init, hm, hh, hn);
+      for (int64_t k = 0; k < tb.n; ++k) {
+        double x = 0.0;
+        if (type == CN_MECH_HH) x = which == 0 ? hm : (which == 1 ? hh : hn);
+        else if (type == CN_MECH_KM) x = km_inf(m->v_init);
+        else x = which == 0 ? cahi_inf(m->v_init) : 5e-5;
+        out[k] = m->fp32 ? (double)(float)x : x;
+      }
+      return CN_OK;
+    }
+    double *buf = nullptr;
+    HIPCHK(hipMalloc(&buf, std::max<int64_t>(1, m->n_comp) * sizeof(double)));
+    std::vector<double> h(m->n_comp);
+    hipError_t e = launch_read_state(m->kp, m->fp32, m->n_comp, m->step, type, which, buf, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e == hipSuccess) e = hipMemcpy(h.data(), buf, m->n_comp * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    HIPCHK(e);
+    for (int64_t k = 0; k < tb.n; ++k) out[k] = h[m->dev_of_node[tb.node[k]]];
+  } catch (const Err &e) {
+    return fail(e.code, e.msg);
+  }
+  return CN_OK;
+}
+
+int cn_model_info(const cn_model *m, cn_info *o) {
+  if (!m || !o) return fail(CN_E_INVALID, "NULL argument");
+  std::memset(o, 0, sizeof *o);
+  o->n_comp = m->n_comp;
+  o->n_syn = m->n_syn;
+  o->n_netcon = m->n_nc;
+  o->n_groups = m->n_groups;
+  o->step = m->step;
+  o->device_bytes = m->device_bytes;
+  o->n_cells = m->n_cells;
+  o->interval_steps = m->dt_fixed ? m->kp.M : 0;
+  o->group_threads = m->threads;
+  o->group_slots = m->slots;
+  o->max_group_nodes = m->max_group_nodes;
+  o->max_levels = m->max_levels;
+  o->ring_slots = m->dt_fixed ? m->kp.ring : 0;
+  o->event_capacity = m->dt_fixed ? m->kp.ev_cap : 0;
+  o->precision = m->fp32 ? CN_PREC_FP32_MECH : CN_PREC_FP64;
+  o->lds_bytes = m->lds_bytes;
+  o->dt = m->dt;
+  return CN_OK;
+}
+
+int cn_stats(const cn_model *m, double *kernel_ms, int64_t *kernel_launches) {
+  if (!m) return fail(CN_E_INVALID, "model is NULL");
+  if (kernel_ms) *kernel_ms = m->kernel_ms;
+  if (kernel_launches) *kernel_launches = m->kernel_launches;
+  return CN_OK;
+}
+
+void cn_model_destroy(cn_model *m) { delete m; }
+
+}  // extern "C"

@@ -89,6 +89,7 @@ class Model:
     dt: float = 0.025
     tstop: float = 100.0
     name: str = ""
+    poisson_key: Optional[np.ndarray] = None  # int64 [n_syn] background stream ids (None: instance index)
 
     @property
     def n_comp(self) -> int:
@@ -285,6 +286,8 @@ def subset_cells(m: Model, cells: np.ndarray) -> Model:
     nck = (cell_map[m.nc_src] >= 0) & (syn_map[m.nc_syn] >= 0) if m.nc_src.shape[0] else np.zeros(0, bool)
     kk = syn_map[m.kick_syn] >= 0 if m.kick_syn.shape[0] else np.zeros(0, bool)
     pw = m.poisson_weight[syn_map >= 0] if m.poisson_weight.shape[0] else m.poisson_weight
+    old_key = m.poisson_key if m.poisson_key is not None else np.arange(syn_map.shape[0], dtype=np.int64)
+    pkey = old_key[syn_map >= 0]
     return Model(
         n_cells=int(cells.shape[0]), cell_offset=off, parent=m.parent[old_nodes], area=m.area[old_nodes],
         ri=m.ri[old_nodes], cm=m.cm[old_nodes], v_init=m.v_init, celsius=m.celsius, mechs=mechs,
@@ -292,4 +295,4 @@ def subset_cells(m: Model, cells: np.ndarray) -> Model:
         nc_weight=m.nc_weight[nck], nc_delay=m.nc_delay[nck], threshold=m.threshold[cells],
         kick_step=m.kick_step[kk], kick_syn=syn_map[m.kick_syn[kk]], kick_weight=m.kick_weight[kk],
         poisson_rate_hz=m.poisson_rate_hz, poisson_weight=pw, seed=m.seed, dt=m.dt, tstop=m.tstop,
-        name=m.name + "-subset")
+        name=m.name + "-subset", poisson_key=pkey)
