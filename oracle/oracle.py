@@ -14,6 +14,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
+# The same source compiled with fused multiply-add contraction: an equally valid oracle that rounds differently at
+# every step. Tests use it to measure how strongly a network amplifies rounding-level differences.
+LIB_FMA_PATH = os.path.join(HERE, "liborc_fma.so")
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -40,24 +43,26 @@ class OrcSpec(C.Structure):
 
 
 def build(force: bool = True) -> str:
-    """Compile liborc.so with gcc: plain -O2, no FMA contraction, OpenMP over cells."""
-    if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-Wall",
-               "-Wno-unused-function", os.path.join(HERE, "orc.c"), "-o", LIB_PATH + ".tmp", "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    """Compile liborc.so with gcc: plain -O2, no FMA contraction, OpenMP over cells; and liborc_fma.so, the same
+    source with FMA contraction."""
+    for path, fp in ((LIB_PATH, ["-ffp-contract=off"]), (LIB_FMA_PATH, ["-mfma", "-ffp-contract=fast"])):
+        if force or not os.path.exists(path):
+            cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp"] + fp + [
+                "-Wall", "-Wno-unused-function", os.path.join(HERE, "orc.c"), "-o", path + ".tmp", "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(path + ".tmp", path)
     return LIB_PATH
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
-        L = C.CDLL(LIB_PATH)
+def lib(fma: bool = False):
+    path = LIB_FMA_PATH if fma else LIB_PATH
+    if path not in _libs:
+        if not os.path.exists(path):
+            build(force=False)
+        L = C.CDLL(path)
         L.orc_error.restype = C.c_char_p
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(OrcSpec)]
@@ -79,8 +84,8 @@ def lib():
         L.orc_poisson_draw.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64]
         L.orc_poisson_draw.restype = C.c_uint32
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _p(a, t):
@@ -91,8 +96,9 @@ class OracleSim:
     """One oracle simulation of a ``synth.Model``. ``batch_steps``: 0 inserts a spike's events at once; M > 0
     inserts them at the end of each M-step interval."""
 
-    def __init__(self, model, dt=None, batch_steps=0, n_threads=1, keep_matrix=False):
+    def __init__(self, model, dt=None, batch_steps=0, n_threads=1, keep_matrix=False, fma=False):
         self.model = model
+        self._L = lib(fma)
         dt = float(model.dt if dt is None else dt)
         n = model.n_comp
         keep = []
@@ -151,43 +157,43 @@ class OracleSim:
         s.n_threads = int(n_threads)
         s.keep_matrix = 1 if keep_matrix else 0
         self.dt = dt
-        self._h = lib().orc_create(C.byref(s))
+        self._h = self._L.orc_create(C.byref(s))
         if not self._h:
-            raise ValueError("oracle: " + lib().orc_error().decode())
+            raise ValueError("oracle: " + self._L.orc_error().decode())
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_destroy(h)
+            self._L.orc_destroy(h)
             self._h = None
 
     @property
     def step(self) -> int:
-        return int(lib().orc_step(self._h))
+        return int(self._L.orc_step(self._h))
 
     def run_to_step(self, n: int):
-        if lib().orc_run(self._h, int(n)) != 0:
-            raise RuntimeError("oracle: " + lib().orc_error().decode())
+        if self._L.orc_run(self._h, int(n)) != 0:
+            raise RuntimeError("oracle: " + self._L.orc_error().decode())
 
     def run(self, tstop: float):
         self.run_to_step(int(round(tstop / self.dt)))
 
     def v(self) -> np.ndarray:
         out = np.empty(self.model.n_comp)
-        lib().orc_get_v(self._h, _p(out, C.c_double))
+        self._L.orc_get_v(self._h, _p(out, C.c_double))
         return out
 
     def spikes(self):
-        n = int(lib().orc_n_spikes(self._h))
+        n = int(self._L.orc_n_spikes(self._h))
         gid = np.empty(n, np.int32)
         step = np.empty(n, np.int64)
         t = np.empty(n)
         if n:
-            lib().orc_get_spikes(self._h, _p(gid, C.c_int32), _p(step, C.c_int64), _p(t, C.c_double))
+            self._L.orc_get_spikes(self._h, _p(gid, C.c_int32), _p(step, C.c_int64), _p(t, C.c_double))
         return gid, step, t
 
     def n_delivered(self) -> int:
-        return int(lib().orc_n_delivered(self._h))
+        return int(self._L.orc_n_delivered(self._h))
 
     def states(self) -> dict:
         n = self.model.n_comp
@@ -196,14 +202,14 @@ class OracleSim:
         out = {"hh_m": np.empty(cnt["hh"]), "hh_h": np.empty(cnt["hh"]), "hh_n": np.empty(cnt["hh"]),
                "km_n": np.empty(cnt["km"]), "cahi_m": np.empty(cnt["cahi"]), "cahi_cai": np.empty(cnt["cahi"]),
                "syn_g": np.empty(cnt["expsyn"])}
-        lib().orc_get_states(self._h, *[_p(out[k], C.c_double) for k in
+        self._L.orc_get_states(self._h, *[_p(out[k], C.c_double) for k in
                                         ("hh_m", "hh_h", "hh_n", "km_n", "cahi_m", "cahi_cai", "syn_g")])
         return out
 
     def last_matrix(self):
         n = self.model.n_comp
         d, rhs, dv = np.empty(n), np.empty(n), np.empty(n)
-        lib().orc_get_last_matrix(self._h, _p(d, C.c_double), _p(rhs, C.c_double), _p(dv, C.c_double))
+        self._L.orc_get_last_matrix(self._h, _p(d, C.c_double), _p(rhs, C.c_double), _p(dv, C.c_double))
         return d, rhs, dv
 
 
