@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--n-cells", type=int, default=50000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     def log(msg):
@@ -118,6 +120,15 @@ def main():
         log("bench.py needs a GPU")
         sys.exit(1)
     from paper_1901_10975_amd import synth
+
+    if args.copy_probe:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {a.numel() * 4} bytes read and written")
+        del a, b
 
     t0 = time.time()
     m = synth.config3(n_cells=args.n_cells)

@@ -24,6 +24,7 @@ namespace cn {
 hipError_t launch_interval(const KParams &p, bool fp32, int threads, int slots, int lds_bytes, hipStream_t st);
 hipError_t set_interval_lds(bool fp32, int threads, int slots, int lds_bytes);
 hipError_t launch_advance(int64_t *ctl, int32_t M, hipStream_t st);
+hipError_t launch_fanout(const KParams &p, hipStream_t st);
 hipError_t launch_set_ctl(int64_t *ctl, int64_t n_begin, int64_t n_target, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *ptr, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_read_state(const KParams &p, bool fp32, int64_t n_nodes, int64_t step, int type, int which,
@@ -116,7 +117,13 @@ struct cn_model {
   std::vector<int64_t> dev_of_syn, syn_of_dev;    // caller ExpSyn <-> device synapse
   std::vector<int64_t> icl_of_dev;                // device IClamp -> caller instance
   std::vector<int32_t> cell_of_devcell;           // device cell slot -> caller cell
-  std::vector<double> host_b;                     // b per device node (for the dt-dependent diagonal term)
+  // per device node, kept for the dt-dependent node records
+  std::vector<double> host_a, host_b, host_sa;
+  std::vector<uint8_t> host_mf;
+  std::vector<int32_t> host_par;
+  std::vector<uint32_t> host_ch;
+  std::vector<uint64_t> host_syn_key;
+  std::vector<double> host_syn_e, host_syn_wbg;
   int32_t max_levels = 0, max_group_syn = 0, max_group_nodes = 0;
 
   // ---- device
@@ -548,50 +555,40 @@ static void build_tables(cn_model *m) {
     }
   }
   KParams &p = m->kp;
+  m->host_a = a;
   m->host_b = b;
-  p.nd_a = m->upload(a);
-  p.nd_b = m->upload(b);
-  p.nd_sa = m->upload(sa);
-  p.nd_par = m->upload(par);
-  p.nd_ch = m->upload(ch);
-  p.nd_mf = m->upload(mf);
+  m->host_sa = sa;
+  m->host_mf = mf;
+  m->host_par = par;
+  m->host_ch = ch;
   p.v = m->upload(std::vector<double>(N, m->v_init));
-  for (int k = 0; k < 6; ++k) p.st[k] = m->upload_s(st[k]);
-  auto col = [&](int t, int j, const double **arr, double *sc) {
-    const Table &tb = m->mech[t];
-    *arr = nullptr;
-    *sc = tb.present ? tb.p[j].s : 0.0;
-    if (tb.present && !tb.p[j].uniform) *arr = m->upload(prm[t][j]);
-  };
-  col(CN_MECH_HH, 0, &p.hh_gna, &p.hh_gna_s);
-  col(CN_MECH_HH, 1, &p.hh_gk, &p.hh_gk_s);
-  col(CN_MECH_HH, 2, &p.hh_gl, &p.hh_gl_s);
-  col(CN_MECH_HH, 3, &p.hh_el, &p.hh_el_s);
-  // the kernel reads all four hh columns from arrays when any one is not uniform
-  if (p.hh_gna || p.hh_gk || p.hh_gl || p.hh_el) {
-    const Table &tb = m->mech[CN_MECH_HH];
-    const double **arrs[4] = {&p.hh_gna, &p.hh_gk, &p.hh_gl, &p.hh_el};
-    for (int j = 0; j < 4; ++j)
-      if (!*arrs[j]) {
-        std::vector<double> v(N, 0.0);
-        for (int64_t k = 0; k < tb.n; ++k) v[m->dev_of_node[tb.node[k]]] = tb.p[j].v[k];
-        *arrs[j] = m->upload(v);
-      }
+  p.st_stride = N;
+  {
+    std::vector<double> all(6 * (size_t)N);
+    for (int k = 0; k < 6; ++k) std::copy(st[k].begin(), st[k].end(), all.begin() + (size_t)k * N);
+    p.st = m->upload_s(all);
   }
-  col(CN_MECH_PAS, 0, &p.pas_g, &p.pas_g_s);
-  col(CN_MECH_PAS, 1, &p.pas_e, &p.pas_e_s);
-  if (p.pas_g || p.pas_e) {
-    const Table &tb = m->mech[CN_MECH_PAS];
-    const double **arrs[2] = {&p.pas_g, &p.pas_e};
-    for (int j = 0; j < 2; ++j)
-      if (!*arrs[j]) {
-        std::vector<double> v(N, 0.0);
-        for (int64_t k = 0; k < tb.n; ++k) v[m->dev_of_node[tb.node[k]]] = tb.p[j].v[k];
-        *arrs[j] = m->upload(v);
+  // density-mechanism parameters: scalars when every column is uniform, else a per-node table of all columns
+  {
+    const int cols[N_PRM][2] = {{CN_MECH_HH, 0}, {CN_MECH_HH, 1}, {CN_MECH_HH, 2}, {CN_MECH_HH, 3},
+                                {CN_MECH_PAS, 0}, {CN_MECH_PAS, 1}, {CN_MECH_KM, 0}, {CN_MECH_CAHI, 0}};
+    bool any = false;
+    for (int c = 0; c < N_PRM; ++c) {
+      const Table &tb = m->mech[cols[c][0]];
+      p.prm_s[c] = tb.present ? tb.p[cols[c][1]].s : 0.0;
+      if (tb.present && !tb.p[cols[c][1]].uniform) any = true;
+    }
+    p.prm = nullptr;
+    if (any) {
+      std::vector<double> t(N_PRM * (size_t)N, 0.0);
+      for (int c = 0; c < N_PRM; ++c) {
+        const Table &tb = m->mech[cols[c][0]];
+        if (!tb.present) continue;
+        for (int64_t k = 0; k < tb.n; ++k) t[(size_t)c * N + m->dev_of_node[tb.node[k]]] = tb.p[cols[c][1]].v[k];
       }
+      p.prm = m->upload(t);
+    }
   }
-  col(CN_MECH_KM, 0, &p.km_g, &p.km_g_s);
-  col(CN_MECH_CAHI, 0, &p.ca_g, &p.ca_g_s);
 
   // point processes in device order: per node, instances in ascending caller index
   auto order_pp = [&](const Table &tb, std::vector<int64_t> &of_dev, std::vector<int64_t> *dev_of) {
@@ -638,22 +635,32 @@ static void build_tables(cn_model *m) {
   }
   check_ranges(m, nd_syn, true);
   check_ranges(m, nd_icl, false);
-  p.nd_syn = m->upload(nd_syn);
-  p.nd_icl = m->upload(nd_icl);
   {
-    std::vector<double> g0(syn.n, 0.0), e(syn.n), wbg(syn.n, 0.0);
-    std::vector<int64_t> sid(syn.n);
+    std::vector<NodeIdx> nx(N);
+    std::vector<int32_t> icl0(N, 0);
+    for (int64_t dn = 0; dn < N; ++dn) {
+      if (nd_syn[dn].y > MAX_NODE_SYN) throw Err{CN_E_INVALID, "more than 65535 synapses on one compartment"};
+      if (nd_icl[dn].y > MAX_NODE_ICL) throw Err{CN_E_INVALID, "more than 255 IClamps on one compartment"};
+      nx[dn].par = m->host_par[dn];
+      nx[dn].ch = m->host_ch[dn];
+      nx[dn].syn0 = nd_syn[dn].x;
+      nx[dn].pk = (uint32_t)nd_syn[dn].y | ((uint32_t)nd_icl[dn].y << 16) | ((uint32_t)m->host_mf[dn] << 24);
+      icl0[dn] = nd_icl[dn].x;
+    }
+    p.nidx = m->upload(nx);
+    p.nd_icl0 = m->upload(icl0);
+  }
+  {
+    m->host_syn_key.assign(syn.n, 0);
+    m->host_syn_e.assign(syn.n, 0.0);
+    m->host_syn_wbg.assign(syn.n, 0.0);
     for (int64_t d = 0; d < syn.n; ++d) {
       const int64_t k = m->syn_of_dev[d];
-      e[d] = syn.p[1].v[k];
-      sid[d] = m->pkey.empty() ? k : m->pkey[k];
-      if (m->rate > 0.0) wbg[d] = m->pw[k];
+      m->host_syn_e[d] = syn.p[1].v[k];
+      m->host_syn_key[d] = (uint64_t)(m->pkey.empty() ? k : m->pkey[k]);
+      if (m->rate > 0.0) m->host_syn_wbg[d] = m->pw[k];
     }
-    p.syn_g = m->upload_s(g0);
-    p.syn_e_s = syn.n ? syn.p[1].s : 0.0;
-    p.syn_e = (syn.n && !syn.p[1].uniform) ? m->upload(e) : nullptr;
-    p.syn_id = m->upload(sid);
-    p.syn_wbg = m->upload_s(wbg);
+    p.syn_g = m->upload_s(std::vector<double>(syn.n, 0.0));
   }
   // cells in device order
   {
@@ -743,33 +750,40 @@ static void prepare_dt(cn_model *m, double dt) {
   {
     std::vector<double> k(N);
     // capacitance term 1e-3 cm/dt (S/cm^2) and the node's own axial coupling -b
-    for (int64_t dn = 0; dn < N; ++dn) k[dn] = 1e-3 * m->cm[m->node_of_dev[dn]] / dt - m->host_b[dn];
-    p.nd_k = m->upload(k);
+    std::vector<NodeRec> rec(N);
+    for (int64_t dn = 0; dn < N; ++dn) {
+      k[dn] = 1e-3 * m->cm[m->node_of_dev[dn]] / dt - m->host_b[dn];
+      rec[dn] = NodeRec{m->host_a[dn], m->host_b[dn], k[dn], m->host_sa[dn]};
+    }
+    p.nrec = m->upload(rec);
   }
   const Table &syn = m->mech[CN_MECH_EXPSYN];
   {
+    // synapse records: stream id, reversal, background weight, decay factor exp(-dt/tau)
     std::vector<double> f(syn.n);
-    bool uni = true;
-    for (int64_t d = 0; d < syn.n; ++d) {
-      f[d] = std::exp(-dt / syn.p[0].v[m->syn_of_dev[d]]);
-      if (f[d] != f[0]) uni = false;
+    for (int64_t d = 0; d < syn.n; ++d) f[d] = std::exp(-dt / syn.p[0].v[m->syn_of_dev[d]]);
+    if (m->fp32) {
+      std::vector<SynRec<float>> r(syn.n);
+      for (int64_t d = 0; d < syn.n; ++d)
+        r[d] = SynRec<float>{m->host_syn_key[d], m->host_syn_e[d], (float)m->host_syn_wbg[d], (float)f[d]};
+      p.syn = m->upload(r);
+    } else {
+      std::vector<SynRec<double>> r(syn.n);
+      for (int64_t d = 0; d < syn.n; ++d) r[d] = SynRec<double>{m->host_syn_key[d], m->host_syn_e[d], m->host_syn_wbg[d], f[d]};
+      p.syn = m->upload(r);
     }
-    p.syn_f_s = syn.n ? f[0] : 0.0;
-    p.syn_f = (syn.n && !uni) ? m->upload_s(f) : nullptr;
   }
   const Table &icl = m->mech[CN_MECH_ICLAMP];
   {
-    std::vector<double> cur(icl.n);
-    std::vector<int64_t> on(icl.n), off(icl.n);
+    std::vector<IclRec> r(icl.n);
     for (int64_t d = 0; d < icl.n; ++d) {
       const int64_t k = m->icl_of_dev[d];
-      cur[d] = 100.0 * icl.p[2].v[k] / m->area[icl.node[k]];
-      on[d] = (int64_t)std::ceil(icl.p[0].v[k] / dt - 0.5);
-      off[d] = (int64_t)std::ceil((icl.p[0].v[k] + icl.p[1].v[k]) / dt - 0.5);
+      r[d].cur = 100.0 * icl.p[2].v[k] / m->area[icl.node[k]];
+      r[d].on = (int64_t)std::ceil(icl.p[0].v[k] / dt - 0.5);
+      r[d].off = (int64_t)std::ceil((icl.p[0].v[k] + icl.p[1].v[k]) / dt - 0.5);
+      r[d].pad = 0.0;
     }
-    p.icl_cur = m->upload(cur);
-    p.icl_on = m->upload(on);
-    p.icl_off = m->upload(off);
+    p.icl = m->upload(r);
   }
   // delays in steps, interval length M, ring of interval slots
   int64_t minD = INT64_MAX, maxD = 0;
@@ -813,6 +827,8 @@ static void prepare_dt(cn_model *m, double dt) {
   }
   if (sb >= INT32_MAX) throw Err{CN_E_INVALID, "model too large for the spike scratch"};
   p.gsp_pack = static_cast<int32_t *>(m->dalloc(sb * sizeof(int32_t)));
+  p.gsp_cnt = static_cast<int32_t *>(m->dalloc(m->n_groups * sizeof(int32_t)));
+  HIPCHK(launch_fill_i32(p.gsp_cnt, m->n_groups, 0, m->stream));
   p.gsp_frac = static_cast<double *>(m->dalloc(sb * sizeof(double)));
   // spike record drained to the host every drain_every chunks
   const int64_t per_chunk = (int64_t)m->n_cells * per_cell;
@@ -830,20 +846,22 @@ static void prepare_dt(cn_model *m, double dt) {
   p.rec_t = static_cast<double *>(m->dalloc(rc * sizeof(double)));
   p.ctl = static_cast<int64_t *>(m->dalloc(4 * sizeof(int64_t)));
   p.groups = m->upload(m->groups);
-  // LDS: v, s1, s2 (doubles), synaptic g, event keys, step segments, counters
-  const int ssz = m->fp32 ? 4 : 8;
-  p.smax = std::max<int32_t>(8, (m->max_group_syn + 7) / 8 * 8);
-  int off = 24 * m->nmax;
-  p.lds_syn_off = off;
-  off += p.smax * ssz;
-  off = (off + 15) / 16 * 16;
+  // LDS: five rows of doubles per node, event keys, step segments, level starts, background bits, counters
+  p.nmax = m->nmax;
+  int off = 40 * m->nmax;
   p.lds_ev_off = off;
   off += p.ev_cap * 8;
   p.lds_seg_off = off;
   off += (p.M + 1) * 4;
+  p.lds_lvl_off = off;
+  off += (m->max_levels + 1) * 4;
+  p.lds_bg_off = off;
+  off += std::max<int32_t>(m->max_group_syn, 1);
   off = (off + 15) / 16 * 16;
   p.lds_misc_off = off;
   off += 16;
+  p.lds_cst_off = off;
+  off += N_CST * 8;
   m->lds_bytes = off;
   if (m->lds_bytes > 160 * 1024)
     throw Err{CN_E_INVALID, "cell groups need " + std::to_string(m->lds_bytes) + " bytes of LDS (event_capacity "
@@ -853,6 +871,7 @@ static void prepare_dt(cn_model *m, double dt) {
   if (m->opt.use_graph) {
     HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = launch_interval(m->kp, m->fp32, m->threads, m->slots, m->lds_bytes, m->stream);
+    if (e1 == hipSuccess) e1 = launch_fanout(m->kp, m->stream);
     hipError_t e2 = launch_advance(p.ctl, p.M, m->stream);
     hipError_t e3 = hipStreamEndCapture(m->stream, &m->graph);
     HIPCHK(e1);
@@ -1012,6 +1031,7 @@ int cn_run(cn_model *m, double tstop, double dt) {
         HIPCHK(hipGraphLaunch(m->gexec, m->stream));
       } else {
         HIPCHK(launch_interval(p, m->fp32, m->threads, m->slots, m->lds_bytes, m->stream));
+        HIPCHK(launch_fanout(p, m->stream));
         HIPCHK(launch_advance(p.ctl, p.M, m->stream));
       }
       if (timing) HIPCHK(hipEventRecord(m->ev_pool[2 * since + 1], m->stream));

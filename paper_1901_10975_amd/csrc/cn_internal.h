@@ -4,7 +4,7 @@
 // interval (cells do not interact inside an interval, Sec. 2). Inside a group the compartments are stored level by
 // level (all roots, then all depth-1 nodes, ...), children of one parent contiguous and in ascending cell-local
 // index: the constant-depth ordering of Sec. 4.4, which here lets each level of the tree elimination run in
-// parallel. Node q of a group is handled by thread q % T in register slot q / T.
+// parallel, one thread per node of the level.
 #pragma once
 #include <stdint.h>
 
@@ -21,6 +21,40 @@ constexpr uint32_t EV_SYN_MASK = 0x3FFFFFu;
 constexpr uint32_t EV_KIND_NETCON = 0x80000000u;
 constexpr int MAX_INTERVAL = 1023;
 constexpr int64_t MAX_GROUP_SYN = (int64_t)EV_SYN_MASK + 1;
+constexpr int MAX_NODE_SYN = 0xFFFF;  // synapses on one compartment
+constexpr int MAX_NODE_ICL = 0xFF;    // IClamps on one compartment
+
+// per-node constants of the tree matrix (S/cm^2): a (row parent, column node), b (row node, column parent),
+// k = 1e-3 cm/dt - b (capacitance and the node's own axial term on the diagonal), sa = 100/area (point processes)
+struct NodeRec {
+  double a, b, k, sa;
+};
+// per-node indices: parent (group-local, -1 at roots), children (first | count << 16, group-local), first synapse
+// (group-local) and pk = synapse count | IClamp count << 16 | mechanism flags << 24
+struct NodeIdx {
+  int32_t par;
+  uint32_t ch;
+  int32_t syn0;
+  uint32_t pk;
+};
+
+// synapse record (device order): background stream id, reversal potential, background weight and decay factor
+template <typename S>
+struct SynRec {
+  uint64_t key;
+  double e;
+  S wbg;
+  S f;
+};
+// IClamp record (device order): on for steps on <= n < off, current density 100 amp / area (mA/cm^2)
+struct IclRec {
+  int64_t on, off;
+  double cur;
+  double pad;
+};
+
+// constants the interval kernel keeps in LDS (indices into a small double table)
+enum { C_PRM = 0, C_Q10DT = 8, C_DT, C_CA_FM, C_CA_FR, C_CA_K, N_CST };
 
 struct GroupDesc {
   int64_t node_base;  // first node of the group in the node arrays
@@ -30,6 +64,9 @@ struct GroupDesc {
   int32_t spk_base, icl_base, pad0, pad1;
 };
 
+// non-uniform density-mechanism parameters, columns of the per-node parameter table
+enum { P_HH_GNA = 0, P_HH_GK, P_HH_GL, P_HH_EL, P_PAS_G, P_PAS_E, P_KM_G, P_CA_G, N_PRM };
+
 struct KParams {
   const GroupDesc *groups;
   const int32_t *lvl_start;  // per group n_levels + 1 group-local starts
@@ -37,32 +74,23 @@ struct KParams {
   int32_t M;     // steps per interval
   int32_t ring;  // interval slots in the event ring
   int32_t ev_cap;
-  int32_t smax;  // LDS synapse slots per group
-  int32_t lds_ev_off, lds_seg_off, lds_misc_off, lds_syn_off;  // byte offsets into dynamic LDS
+  int32_t nmax;  // nodes per group (LDS rows)
   int32_t has_bg;
-  // node arrays (device order)
-  const double *nd_a, *nd_b, *nd_k, *nd_sa;
-  const int32_t *nd_par;
-  const uint32_t *nd_ch;   // first child (low 16 bits) | child count (high 16 bits), group-local
-  const uint8_t *nd_mf;    // MF_* flags
-  const int2 *nd_syn;      // group-local synapse range (start, count)
-  const int2 *nd_icl;      // group-local IClamp range (start, count)
+  int32_t lds_ev_off, lds_seg_off, lds_lvl_off, lds_bg_off, lds_misc_off, lds_cst_off;
+  // node tables (device order)
+  const NodeRec *nrec;
+  const NodeIdx *nidx;
+  const int32_t *nd_icl0;  // group-local first IClamp of each node
   double *v;
-  void *st[6];             // hh m, h, n; km n; cahi m, cai (double or float, one per node)
-  // per-node parameters, NULL when the column is uniform (then the scalar is used)
-  const double *hh_gna, *hh_gk, *hh_gl, *hh_el, *pas_g, *pas_e, *km_g, *ca_g;
-  double hh_gna_s, hh_gk_s, hh_gl_s, hh_el_s, pas_g_s, pas_e_s, km_g_s, ca_g_s;
+  void *st;                // states: 6 arrays of st_stride elements (hh m, h, n; km n; cahi m, cai), double or float
+  int64_t st_stride;
+  const double *prm;       // N_PRM columns of st_stride values, or NULL when every column is uniform
+  double prm_s[N_PRM];     // the uniform values
   // synapses (device order)
   void *syn_g;             // double or float
-  const double *syn_e;     // NULL: syn_e_s
-  double syn_e_s;
-  const void *syn_f;       // decay factor exp(-dt/tau), double or float; NULL: syn_f_s
-  double syn_f_s;
-  const int64_t *syn_id;   // caller's instance index (background stream key)
-  const void *syn_wbg;     // background weight, double or float
+  const void *syn;         // SynRec<double> or SynRec<float>
   // IClamp (device order)
-  const double *icl_cur;   // 100 amp / area, mA/cm^2
-  const int64_t *icl_on, *icl_off;
+  const IclRec *icl;
   // cells (device order)
   const int32_t *cell_gid;
   const double *cell_theta;
@@ -78,6 +106,7 @@ struct KParams {
   int32_t *ev_cnt;         // [ring * n_groups]
   uint64_t *ev_key;        // [ring * n_groups * ev_cap]
   // spikes
+  int32_t *gsp_cnt;        // per group: spikes of the last chunk
   int32_t *gsp_pack;       // per group scratch: cell | (step in interval << 16)
   double *gsp_frac;
   int32_t *rec_cnt;

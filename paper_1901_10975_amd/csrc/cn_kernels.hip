@@ -22,28 +22,10 @@
 namespace cn {
 
 // ------------------------------------------------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64 multiplies that mix the counter
-// under a key bumped by Weyl constants. Background event for (synapse s, step n): word n % 4 of
-// Philox(counter = (s lo, s hi, n/4 lo, n/4 hi), key = (seed lo, seed hi)) below the rate threshold.
-__device__ __forceinline__ uint32_t bg_word(uint64_t seed, uint64_t syn, uint64_t step) {
-  const uint64_t blk = step >> 2;
-  uint32_t c0 = (uint32_t)syn, c1 = (uint32_t)(syn >> 32), c2 = (uint32_t)blk, c3 = (uint32_t)(blk >> 32);
-  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-  const int w = (int)(step & 3);
-  return w == 0 ? c0 : (w == 1 ? c1 : (w == 2 ? c2 : c3));
-}
+// Background events: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), ten rounds of two 32x32->64 multiplies
+// that mix the counter under a key bumped by Weyl constants. The event of (synapse stream k, step n) is word n % 4
+// of Philox(counter = (k lo, k hi, n/4 lo, n/4 hi), key = (seed lo, seed hi)) below the rate threshold, so one call
+// serves four consecutive steps (bg_mask4 below).
 
 // ------------------------------------------------------------------------------------------------------------------
 // Mechanism kinetics. S is the state type: double on the FP64 path, float on the FP32-mechanism path (rates and
@@ -53,19 +35,28 @@ struct Math;
 template <>
 struct Math<double> {
   static __device__ __forceinline__ double ex(double x) { return exp(x); }
-  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  // reciprocal: hardware estimate refined by two Newton steps (error within an ulp or two of 1/x)
+  static __device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+  }
   // 1 - exp(-z)
   static __device__ __forceinline__ double omx(double z) { return 1.0 - exp(-z); }
 };
 template <>
 struct Math<float> {
   static __device__ __forceinline__ float ex(float x) { return __expf(x); }
-  static __device__ __forceinline__ float rcp(float x) { return __fdividef(1.0f, x); }
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
   // 1 - exp(-z) without the cancellation of the subtraction at small z (four-term series below 0.03)
   static __device__ __forceinline__ float omx(float z) {
     return z < 0.03f ? z * (1.0f - z * 0.5f * (1.0f - z * (1.0f / 3.0f) * (1.0f - 0.25f * z))) : 1.0f - __expf(-z);
   }
 };
+
+__device__ __forceinline__ double rcp64(double x) { return Math<double>::rcp(x); }
 
 constexpr double E_NEG_1P5 = 0.22313016014842982893;  // exp(-1.5)
 constexpr double E_POS_0P5 = 1.64872127070012814685;  // exp(0.5)
@@ -130,18 +121,50 @@ __device__ __forceinline__ void stv(void *p, int64_t i, S x) {
 
 __device__ __forceinline__ uint32_t ev_syn(uint64_t k) { return (uint32_t)(k >> EV_SYN_SHIFT) & EV_SYN_MASK; }
 
+// background-event bits of synapse stream `key` for the four steps 4*blk .. 4*blk+3
+__device__ __forceinline__ uint32_t bg_mask4(uint64_t seed, uint64_t key, uint64_t blk, uint64_t thresh) {
+  uint32_t c0 = (uint32_t)key, c1 = (uint32_t)(key >> 32), c2 = (uint32_t)blk, c3 = (uint32_t)(blk >> 32);
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return ((uint64_t)c0 < thresh ? 1u : 0u) | ((uint64_t)c1 < thresh ? 2u : 0u) | ((uint64_t)c2 < thresh ? 4u : 0u) |
+         ((uint64_t)c3 < thresh ? 8u : 0u);
+}
+
 // ------------------------------------------------------------------------------------------------------------------
-template <int T, int K, typename S>
+// LDS: five rows of nmax doubles per group -
+//   v_l  membrane potential;
+//   w_l  d (diagonal) after assembly, then w = b/d after elimination;
+//   u_l  rhs after assembly, then u = rhs/d after elimination;
+//   P_l  the node's contribution a(w + 1) to its parent's diagonal, later the solution x;
+//   Q_l  dv = v_parent - v after assembly, then the contribution a(u - dv) to the parent's rhs.
+// With these, elimination of node i reads d_i, rhs_i and its children's contributions, and back-substitution is
+// x_i = u_i - w_i x_parent.
+template <int T, typename S>
 __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
-  constexpr int NMAX = T * K;
+  const int NMAX = p.nmax;
   double *v_l = reinterpret_cast<double *>(lds);
-  double *s1 = v_l + NMAX;
-  double *s2 = s1 + NMAX;
-  S *g_l = reinterpret_cast<S *>(lds + p.lds_syn_off);
+  double *w_l = v_l + NMAX;
+  double *u_l = w_l + NMAX;
+  double *P_l = u_l + NMAX;
+  double *Q_l = P_l + NMAX;
   uint64_t *ev = reinterpret_cast<uint64_t *>(lds + p.lds_ev_off);
   int *seg = reinterpret_cast<int *>(lds + p.lds_seg_off);
+  int *lv = reinterpret_cast<int *>(lds + p.lds_lvl_off);
+  uint8_t *bgm = reinterpret_cast<uint8_t *>(lds + p.lds_bg_off);
   int *misc = reinterpret_cast<int *>(lds + p.lds_misc_off);
+  double *cst = reinterpret_cast<double *>(lds + p.lds_cst_off);
 
   const int G = blockIdx.x;
   const int t = threadIdx.x;
@@ -154,16 +177,21 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
   if (n_end <= n_begin) return;
   const int slot = (int)(ival % p.ring);
   const int N = gd.n_nodes;
+  const int D = gd.n_levels;
+  const int n_syn = gd.n_syn;
   const int64_t nb = gd.node_base;
   const int64_t sb = gd.syn_base;
-  const int32_t *lvl = p.lvl_start + gd.lvl_base;
-  const int D = gd.n_levels;
-  const int s_begin = (int)(n_begin - ival * M), s_end = (int)(n_end - ival * M);
 
-  // ---- prologue: voltages and conductances on chip, this interval's events sorted
+  // ---- prologue: voltages and level starts on chip, this interval's events sorted
   for (int q = t; q < N; q += T) v_l[q] = p.v[nb + q];
-  for (int s = t; s < gd.n_syn; s += T) g_l[s] = ld<S>(p.syn_g, sb + s);
+  for (int L = t; L <= D; L += T) lv[L] = p.lvl_start[gd.lvl_base + L];
+  if (t < N_PRM) cst[C_PRM + t] = p.prm_s[t];
   if (t == 0) {
+    cst[C_Q10DT] = p.q10dt;
+    cst[C_DT] = p.dt;
+    cst[C_CA_FM] = p.ca_fm;
+    cst[C_CA_FR] = p.ca_fr;
+    cst[C_CA_K] = p.ca_k;
     int lo = gd.kick_base, hi = gd.kick_base + gd.n_kick;
     int a = lo, b = hi;  // first kick with step >= n_begin
     while (a < b) {
@@ -235,223 +263,251 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
     }
     seg[s] = a;
   }
-  // per-node constants of the tree solve, in registers for the whole chunk
-  double ra[K], rb[K], rd[K], rr[K], rdv[K];
-  int rpar[K];
-  uint32_t rch[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const int q = j * T + t;
-    if (q < N) {
-      ra[j] = p.nd_a[nb + q];
-      rb[j] = p.nd_b[nb + q];
-      rpar[j] = p.nd_par[nb + q];
-      rch[j] = p.nd_ch[nb + q];
-    } else {
-      ra[j] = rb[j] = 0.0;
-      rpar[j] = -1;
-      rch[j] = 0;
-    }
-    rd[j] = 1.0;
-    rr[j] = rdv[j] = 0.0;
-  }
   __syncthreads();
 
-  const S q10dt = (S)p.q10dt;
-  const S sdt = (S)p.dt;
-  const S ca_fm = (S)p.ca_fm, ca_fr = (S)p.ca_fr, ca_k = (S)p.ca_k;
-  const bool has_hh_arr = p.hh_gna != nullptr;
-  const bool has_pas_arr = p.pas_g != nullptr;
+  S *st = static_cast<S *>(p.st);
+  const SynRec<S> *syn = static_cast<const SynRec<S> *>(p.syn) + sb;
+  const int64_t sst = p.st_stride;
+  S *sg = static_cast<S *>(p.syn_g) + sb;
+  const int lv1 = lv[1];
+  if (!p.has_bg)
+    for (int i = t; i < n_syn; i += T) bgm[i] = 0;
 
   for (int64_t n = n_begin; n < n_end; ++n) {
     const int s = (int)(n - ival * M);
-    // ---- A: delivery (Sec. 2, event-driven delivery step)
-    const int e0 = seg[s], e1 = seg[s + 1];
-    if (e1 > e0) {
-      for (int e = e0 + t; e < e1; e += T) {
-        const uint32_t ls = ev_syn(ev[e]);
-        if (e == e0 || ev_syn(ev[e - 1]) != ls) {
-          S g = g_l[ls];
-          for (int e2 = e; e2 < e1; ++e2) {
-            const uint64_t key = ev[e2];
-            if (ev_syn(key) != ls) break;
-            const uint32_t id = (uint32_t)key & 0x7FFFFFFFu;
-            g += ((uint32_t)key & EV_KIND_NETCON) ? ld<S>(p.nc_w, id) : ld<S>(p.kick_w, id);
-          }
-          g_l[ls] = g;
-        }
-      }
-      __syncthreads();
+    // ---- background-event bits for a block of four steps (one Philox call gives four words)
+    if (p.has_bg && (n == n_begin || (n & 3) == 0)) {
+      const uint64_t blk = (uint64_t)n >> 2;
+      for (int i = t; i < n_syn; i += T) bgm[i] = (uint8_t)bg_mask4(p.seed, syn[i].key, blk, p.bg_thresh);
     }
+    // ---- A: delivery (Sec. 2, event-driven delivery step): one thread per synapse run, in key order
+    const int e0 = seg[s], e1 = seg[s + 1];
+    for (int e = e0 + t; e < e1; e += T) {
+      const uint32_t ls = ev_syn(ev[e]);
+      if (e == e0 || ev_syn(ev[e - 1]) != ls) {
+        S g = sg[ls];
+        for (int e2 = e; e2 < e1; ++e2) {
+          const uint64_t key = ev[e2];
+          if (ev_syn(key) != ls) break;
+          const uint32_t id = (uint32_t)key & 0x7FFFFFFFu;
+          g += ((uint32_t)key & EV_KIND_NETCON) ? ld<S>(p.nc_w, id) : ld<S>(p.kick_w, id);
+        }
+        sg[ls] = g;
+      }
+    }
+    __syncthreads();
     // ---- C: states, currents, conductances and the compartment's own axial terms
     const bool pend = n > 0;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const int q = j * T + t;
-      if (q < N) {
-        const int64_t i = nb + q;
-        const double v = v_l[q];
-        double rhs = 0.0, d = 0.0;
-        const uint32_t mf = p.nd_mf[i];
-        if (mf & MF_HH) {
-          S m = ld<S>(p.st[0], i), h = ld<S>(p.st[1], i), nn = ld<S>(p.st[2], i);
-          if (pend) {
-            hh_advance<S>(v, q10dt, m, h, nn);
-            stv<S>(p.st[0], i, m);
-            stv<S>(p.st[1], i, h);
-            stv<S>(p.st[2], i, nn);
-          }
-          const double gnab = has_hh_arr ? p.hh_gna[i] : p.hh_gna_s;
-          const double gkb = has_hh_arr ? p.hh_gk[i] : p.hh_gk_s;
-          const double gl = has_hh_arr ? p.hh_gl[i] : p.hh_gl_s;
-          const double el = has_hh_arr ? p.hh_el[i] : p.hh_el_s;
-          const double gna = (double)((S)gnab * (m * m * m * h));
-          const double gk = (double)((S)gkb * ((nn * nn) * (nn * nn)));
-          rhs -= gna * (v - 50.0) + gk * (v + 77.0) + gl * (v - el);
-          d += gna + gk + gl;
+    const uint32_t bsh = (uint32_t)(n & 3);
+    const S q10dt = (S)cst[C_Q10DT];
+    const S sdt = (S)cst[C_DT];
+    const S ca_fm = (S)cst[C_CA_FM], ca_fr = (S)cst[C_CA_FR], ca_k = (S)cst[C_CA_K];
+#pragma unroll 1
+    for (int q = t; q < N; q += T) {
+      const int64_t i = nb + q;
+      const NodeRec nr = p.nrec[i];
+      const NodeIdx nx = p.nidx[i];
+      const double v = v_l[q];
+      double rhs = 0.0, d = 0.0;
+      const uint32_t mf = nx.pk >> 24;
+      if (mf & MF_HH) {
+        S m = st[i], h = st[sst + i], nn = st[2 * sst + i];
+        if (pend) {
+          hh_advance<S>(v, q10dt, m, h, nn);
+          st[i] = m;
+          st[sst + i] = h;
+          st[2 * sst + i] = nn;
         }
-        if (mf & MF_PAS) {
-          const double g = has_pas_arr ? p.pas_g[i] : p.pas_g_s;
-          const double e = has_pas_arr ? p.pas_e[i] : p.pas_e_s;
-          rhs -= g * (v - e);
-          d += g;
-        }
-        if (mf & MF_KM) {
-          S nk = ld<S>(p.st[3], i);
-          if (pend) {
-            km_advance<S>(v, sdt, nk);
-            stv<S>(p.st[3], i, nk);
-          }
-          const double g = (double)((S)(p.km_g ? p.km_g[i] : p.km_g_s) * nk);
-          rhs -= g * (v + 77.0);
-          d += g;
-        }
-        if (mf & MF_CAHI) {
-          const S gca = (S)(p.ca_g ? p.ca_g[i] : p.ca_g_s);
-          S mc = ld<S>(p.st[4], i);
-          if (pend) {
-            S cai = ld<S>(p.st[5], i);
-            cahi_advance<S>(v, ca_fm, ca_fr, ca_k, gca, mc, cai);
-            stv<S>(p.st[4], i, mc);
-            stv<S>(p.st[5], i, cai);
-          }
-          const double g = (double)(gca * (mc * mc));
-          rhs -= g * (v - 120.0);
-          d += g;
-        }
-        const int2 ic = p.nd_icl[i];
-        for (int c = 0; c < ic.y; ++c) {
-          const int64_t k = gd.icl_base + ic.x + c;
-          if (p.icl_on[k] <= n && n < p.icl_off[k]) rhs += p.icl_cur[k];
-        }
-        const int2 sy = p.nd_syn[i];
-        if (sy.y > 0) {
-          const double sa = p.nd_sa[i];
-          for (int c = 0; c < sy.y; ++c) {
-            const int ls = sy.x + c;
-            const int64_t k = sb + ls;
-            S g = g_l[ls];
-            if (p.has_bg && (uint64_t)bg_word(p.seed, (uint64_t)p.syn_id[k], (uint64_t)n) < p.bg_thresh)
-              g += ld<S>(p.syn_wbg, k);
-            const double e = p.syn_e ? p.syn_e[k] : p.syn_e_s;
-            const double gs = sa * (double)g;
-            rhs -= gs * (v - e);
-            d += gs;
-            const S f = p.syn_f ? ld<S>(p.syn_f, k) : (S)p.syn_f_s;
-            g_l[ls] = g * f;  // decay of this step, applied ahead of the next delivery
-          }
-        }
-        d += p.nd_k[i];
-        double dv = 0.0;
-        if (rpar[j] >= 0) {
-          dv = v_l[rpar[j]] - v;
-          rhs -= rb[j] * dv;
-        }
-        rd[j] = d;
-        rr[j] = rhs;
-        rdv[j] = dv;
+        const double gnab = p.prm ? p.prm[P_HH_GNA * sst + i] : cst[C_PRM + P_HH_GNA];
+        const double gkb = p.prm ? p.prm[P_HH_GK * sst + i] : cst[C_PRM + P_HH_GK];
+        const double gl = p.prm ? p.prm[P_HH_GL * sst + i] : cst[C_PRM + P_HH_GL];
+        const double el = p.prm ? p.prm[P_HH_EL * sst + i] : cst[C_PRM + P_HH_EL];
+        const double gna = (double)((S)gnab * (m * m * m * h));
+        const double gk = (double)((S)gkb * ((nn * nn) * (nn * nn)));
+        rhs -= gna * (v - 50.0) + gk * (v + 77.0) + gl * (v - el);
+        d += gna + gk + gl;
       }
-    }
-    // ---- T: elimination, deepest level first. A node's children publish cb = f b + a and cr = f rhs - a dv,
-    // which fold the axial assembly terms of the parent's row into the elimination update.
-    for (int L = D - 1; L >= 1; --L) {
-      const int lo = lvl[L], hi = lvl[L + 1];
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        if (j * T < hi && j * T + T > lo) {
-          const int q = j * T + t;
-          if (q >= lo && q < hi) {
-            double dd = rd[j], rr_ = rr[j];
-            const int c0 = (int)(rch[j] & 0xFFFFu), cn = (int)(rch[j] >> 16);
-            for (int c = c0; c < c0 + cn; ++c) {
-              dd -= s1[c];
-              rr_ -= s2[c];
-            }
-            const double r = 1.0 / dd;
-            const double f = ra[j] * r;
-            s1[q] = f * rb[j] + ra[j];
-            s2[q] = f * rr_ - ra[j] * rdv[j];
-            rd[j] = r;  // keep 1/d for the substitution
-            rr[j] = rr_;
-          }
+      if (mf & MF_PAS) {
+        const double g = p.prm ? p.prm[P_PAS_G * sst + i] : cst[C_PRM + P_PAS_G];
+        const double e = p.prm ? p.prm[P_PAS_E * sst + i] : cst[C_PRM + P_PAS_E];
+        rhs -= g * (v - e);
+        d += g;
+      }
+      if (mf & MF_KM) {
+        S nk = st[3 * sst + i];
+        if (pend) {
+          km_advance<S>(v, sdt, nk);
+          st[3 * sst + i] = nk;
         }
+        const double g = (double)((S)(p.prm ? p.prm[P_KM_G * sst + i] : cst[C_PRM + P_KM_G]) * nk);
+        rhs -= g * (v + 77.0);
+        d += g;
+      }
+      if (mf & MF_CAHI) {
+        const S gca = (S)(p.prm ? p.prm[P_CA_G * sst + i] : cst[C_PRM + P_CA_G]);
+        S mc = st[4 * sst + i];
+        if (pend) {
+          S cai = st[5 * sst + i];
+          cahi_advance<S>(v, ca_fm, ca_fr, ca_k, gca, mc, cai);
+          st[4 * sst + i] = mc;
+          st[5 * sst + i] = cai;
+        }
+        const double g = (double)(gca * (mc * mc));
+        rhs -= g * (v - 120.0);
+        d += g;
+      }
+      const int n_icl = (int)((nx.pk >> 16) & 0xFFu);
+      if (n_icl) {
+        const IclRec *ic = p.icl + gd.icl_base + p.nd_icl0[i];
+        for (int c = 0; c < n_icl; ++c)
+          if (ic[c].on <= n && n < ic[c].off) rhs += ic[c].cur;
+      }
+      const int n_s = (int)(nx.pk & 0xFFFFu);
+      for (int c = 0; c < n_s; ++c) {
+        const int ls = nx.syn0 + c;
+        const SynRec<S> sr = syn[ls];
+        S g = sg[ls];
+        if ((bgm[ls] >> bsh) & 1u) g += sr.wbg;
+        const double gs = nr.sa * (double)g;
+        rhs -= gs * (v - sr.e);
+        d += gs;
+        sg[ls] = g * sr.f;  // decay of this step, applied ahead of the next delivery
+      }
+      d += nr.k;
+      double dv = 0.0;
+      if (nx.par >= 0) {
+        dv = v_l[nx.par] - v;
+        rhs -= nr.b * dv;
+      }
+      w_l[q] = d;
+      u_l[q] = rhs;
+      Q_l[q] = dv;
+    }
+    __syncthreads();
+    // ---- T: elimination, deepest level first, one thread per node of the level. Node records of the next
+    // (shallower) level are fetched while the current one is processed.
+    int Lc = D - 1;
+    int qn = Lc >= 1 ? lv[Lc] + t : NMAX;
+    NodeRec rn{};
+    uint32_t chn = 0;
+    if (Lc >= 1 && qn < lv[Lc + 1]) {
+      rn = p.nrec[nb + qn];
+      chn = p.nidx[nb + qn].ch;
+    }
+    for (; Lc >= 1; --Lc) {
+      const int lo = lv[Lc], hi = lv[Lc + 1];
+      const NodeRec r = rn;
+      const uint32_t ch = chn;
+      const int q = qn;
+      if (Lc >= 2) {
+        qn = lv[Lc - 1] + t;
+        if (qn < lo) {
+          rn = p.nrec[nb + qn];
+          chn = p.nidx[nb + qn].ch;
+        }
+      }
+      if (q < hi) {
+        double d = w_l[q], rhs = u_l[q];
+        const int c0 = (int)(ch & 0xFFFFu), cn = (int)(ch >> 16);
+        for (int c = c0; c < c0 + cn; ++c) {
+          d -= P_l[c];
+          rhs -= Q_l[c];
+        }
+        const double ri = rcp64(d);
+        const double w = ri * r.b, u = ri * rhs;
+        w_l[q] = w;
+        u_l[q] = u;
+        P_l[q] = r.a * (w + 1.0);
+        Q_l[q] = r.a * (u - Q_l[q]);
+      }
+      for (int q2 = q + T; q2 < hi; q2 += T) {  // levels wider than the group's threads
+        const NodeRec r2 = p.nrec[nb + q2];
+        const uint32_t ch2 = p.nidx[nb + q2].ch;
+        double d = w_l[q2], rhs = u_l[q2];
+        const int c0 = (int)(ch2 & 0xFFFFu), cn = (int)(ch2 >> 16);
+        for (int c = c0; c < c0 + cn; ++c) {
+          d -= P_l[c];
+          rhs -= Q_l[c];
+        }
+        const double ri = rcp64(d);
+        const double w = ri * r2.b, u = ri * rhs;
+        w_l[q2] = w;
+        u_l[q2] = u;
+        P_l[q2] = r2.a * (w + 1.0);
+        Q_l[q2] = r2.a * (u - Q_l[q2]);
       }
       __syncthreads();
     }
-    // ---- R: roots (level 0 holds the group's cells in order)
+    // ---- R: roots (level 0 holds the group's cells in order): solve, v update, threshold detection
+    for (int q = t; q < lv1; q += T) {
+      const uint32_t ch = p.nidx[nb + q].ch;
+      double d = w_l[q], rhs = u_l[q];
+      const int c0 = (int)(ch & 0xFFFFu), cn = (int)(ch >> 16);
+      for (int c = c0; c < c0 + cn; ++c) {
+        d -= P_l[c];
+        rhs -= Q_l[c];
+      }
+      const double x = rhs / d;
+      const double vold = v_l[q];
+      const double vnew = vold + x;
+      v_l[q] = vnew;
+      P_l[q] = x;
+      const double th = p.cell_theta[gd.cell_base + q];
+      if (vold < th && th <= vnew) {
+        const int idx = atomicAdd(&misc[1], 1);
+        p.gsp_pack[gd.spk_base + idx] = q | ((s + 1) << 16);
+        p.gsp_frac[gd.spk_base + idx] = (th - vold) / (vnew - vold);
+      }
+      if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
+    }
+    __syncthreads();
+    // ---- B: substitution, root to leaves: x = u - w x_parent (parents of the next level fetched ahead)
     {
-      const int hi = lvl[1];
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        if (j * T < hi) {
-          const int q = j * T + t;
-          if (q < hi) {
-            double dd = rd[j], rr_ = rr[j];
-            const int c0 = (int)(rch[j] & 0xFFFFu), cn = (int)(rch[j] >> 16);
-            for (int c = c0; c < c0 + cn; ++c) {
-              dd -= s1[c];
-              rr_ -= s2[c];
-            }
-            const double x = rr_ / dd;
-            const double vold = v_l[q];
-            const double vnew = vold + x;
-            v_l[q] = vnew;
-            s1[q] = x;
-            const double th = p.cell_theta[gd.cell_base + q];
-            if (vold < th && th <= vnew) {
-              const int idx = atomicAdd(&misc[1], 1);
-              p.gsp_pack[gd.spk_base + idx] = q | ((s + 1) << 16);
-              p.gsp_frac[gd.spk_base + idx] = (th - vold) / (vnew - vold);
-            }
-            if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
-          }
+      int qb = D > 1 ? lv[1] + t : NMAX;
+      int parn = (D > 1 && qb < lv[2]) ? p.nidx[nb + qb].par : 0;
+      for (int L = 1; L < D; ++L) {
+        const int lo = lv[L], hi = lv[L + 1];
+        const int q = qb, par = parn;
+        if (L + 1 < D) {
+          qb = hi + t;
+          if (qb < lv[L + 2]) parn = p.nidx[nb + qb].par;
         }
-      }
-      __syncthreads();
-    }
-    // ---- B: substitution, root to leaves
-    for (int L = 1; L < D; ++L) {
-      const int lo = lvl[L], hi = lvl[L + 1];
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        if (j * T < hi && j * T + T > lo) {
-          const int q = j * T + t;
-          if (q >= lo && q < hi) {
-            const double x = (rr[j] - rb[j] * s1[rpar[j]]) * rd[j];
-            s1[q] = x;
-            v_l[q] += x;
-          }
+        if (q < hi) {
+          const double x = u_l[q] - w_l[q] * P_l[par];
+          P_l[q] = x;
+          v_l[q] += x;
         }
+        for (int q2 = q + T; q2 < hi; q2 += T) {
+          const double x = u_l[q2] - w_l[q2] * P_l[p.nidx[nb + q2].par];
+          P_l[q2] = x;
+          v_l[q2] += x;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
 
-  // ---- epilogue: write back, record spikes, fan out through NetCons into the event ring
+  // ---- epilogue: write back; the chunk's spikes (count in gsp_cnt) are recorded and fanned out by cn_fanout
   for (int q = t; q < N; q += T) p.v[nb + q] = v_l[q];
-  for (int s = t; s < gd.n_syn; s += T) stv<S>(p.syn_g, sb + s, g_l[s]);
-  const int nsp = misc[1];
-  for (int k = t; k < nsp; k += T) {
+  if (t == 0) {
+    p.gsp_cnt[G] = misc[1];
+    if (n_end == (ival + 1) * (int64_t)M) p.ev_cnt[(int64_t)slot * p.n_groups + G] = 0;
+  }
+}
+
+// Spike record and fan-out of one chunk (Sec. 2 spike exchange, on one device): each spike walks its source cell's
+// NetCons and appends an event key to the ring slot of the interval it is due in. Slots of later intervals only, so
+// it never touches the slot the chunk just consumed (every delay is at least one interval).
+__global__ void __launch_bounds__(256) cn_fanout(const KParams p) {
+  const int G = blockIdx.x;
+  const int t = threadIdx.x;
+  const int nsp = p.gsp_cnt[G];
+  if (nsp == 0) return;
+  const GroupDesc gd = p.groups[G];
+  const int64_t n_begin = p.ctl[0];
+  const int M = p.M;
+  const int64_t ival = n_begin / M;
+  for (int k = t; k < nsp; k += 256) {
     const int pk = p.gsp_pack[gd.spk_base + k];
     const int q = pk & 0xFFFF;
     const int64_t kstep = ival * M + (pk >> 16);
@@ -470,7 +526,7 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
     const int64_t kstep = ival * M + (pk >> 16);
     const int gid = p.cell_gid[gd.cell_base + q];
     const int64_t o0 = p.out_off[gid], o1 = p.out_off[gid + 1];
-    for (int64_t o = o0 + t; o < o1; o += T) {
+    for (int64_t o = o0 + t; o < o1; o += 256) {
       const int nc = p.out_nc[o];
       const int64_t td = kstep + p.nc_D[nc];
       const int64_t it = td / M;
@@ -485,7 +541,6 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
       else atomicOr(&p.flags[FLAG_EV_OVERFLOW], 1);
     }
   }
-  if (t == 0 && n_end == (ival + 1) * (int64_t)M) p.ev_cnt[(int64_t)slot * p.n_groups + G] = 0;
 }
 
 // next chunk: up to the next interval boundary or the target
@@ -517,17 +572,20 @@ __global__ void cn_read_state(const KParams p, int64_t n_nodes, int64_t step, in
   if (i >= n_nodes) return;
   const double v = p.v[i];
   const bool pend = step > 0;
+  const S *st = static_cast<const S *>(p.st);
+  const int64_t sst = p.st_stride;
   if (type == 0) {
-    S m = ld<S>(p.st[0], i), h = ld<S>(p.st[1], i), nn = ld<S>(p.st[2], i);
+    S m = st[i], h = st[sst + i], nn = st[2 * sst + i];
     if (pend) hh_advance<S>(v, (S)p.q10dt, m, h, nn);
     out[i] = which == 0 ? (double)m : (which == 1 ? (double)h : (double)nn);
   } else if (type == 2) {
-    S nk = ld<S>(p.st[3], i);
+    S nk = st[3 * sst + i];
     if (pend) km_advance<S>(v, (S)p.dt, nk);
     out[i] = (double)nk;
   } else if (type == 3) {
-    S mc = ld<S>(p.st[4], i), cai = ld<S>(p.st[5], i);
-    if (pend) cahi_advance<S>(v, (S)p.ca_fm, (S)p.ca_fr, (S)p.ca_k, (S)(p.ca_g ? p.ca_g[i] : p.ca_g_s), mc, cai);
+    S mc = st[4 * sst + i], cai = st[5 * sst + i];
+    const S gca = (S)(p.prm ? p.prm[P_CA_G * sst + i] : p.prm_s[P_CA_G]);
+    if (pend) cahi_advance<S>(v, (S)p.ca_fm, (S)p.ca_fr, (S)p.ca_k, gca, mc, cai);
     out[i] = which == 0 ? (double)mc : (double)cai;
   }
 }
@@ -536,50 +594,31 @@ __global__ void cn_read_state(const KParams p, int64_t n_nodes, int64_t step, in
 // launch wrappers (host side)
 using IntervalFn = void (*)(const KParams);
 
-template <typename S>
-static IntervalFn interval_fn_s(int threads, int slots) {
-  if (threads == 256) {
-    switch (slots) {
-      case 1: return cn_interval<256, 1, S>;
-      case 2: return cn_interval<256, 2, S>;
-      case 4: return cn_interval<256, 4, S>;
-      case 8: return cn_interval<256, 8, S>;
-      default: break;
-    }
-  } else if (threads == 512) {
-    switch (slots) {
-      case 1: return cn_interval<512, 1, S>;
-      case 2: return cn_interval<512, 2, S>;
-      case 4: return cn_interval<512, 4, S>;
-      default: break;
-    }
-  } else if (threads == 128) {
-    switch (slots) {
-      case 1: return cn_interval<128, 1, S>;
-      case 2: return cn_interval<128, 2, S>;
-      case 4: return cn_interval<128, 4, S>;
-      case 8: return cn_interval<128, 8, S>;
-      default: break;
-    }
-  }
+static IntervalFn interval_fn(bool fp32, int threads) {
+  if (threads == 256) return fp32 ? cn_interval<256, float> : cn_interval<256, double>;
+  if (threads == 512) return fp32 ? cn_interval<512, float> : cn_interval<512, double>;
+  if (threads == 128) return fp32 ? cn_interval<128, float> : cn_interval<128, double>;
   return nullptr;
 }
 
-static IntervalFn interval_fn(bool fp32, int threads, int slots) {
-  return fp32 ? interval_fn_s<float>(threads, slots) : interval_fn_s<double>(threads, slots);
-}
-
 hipError_t set_interval_lds(bool fp32, int threads, int slots, int lds_bytes) {
-  IntervalFn fn = interval_fn(fp32, threads, slots);
+  (void)slots;
+  IntervalFn fn = interval_fn(fp32, threads);
   if (!fn) return hipErrorInvalidValue;
   return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                              lds_bytes);
 }
 
 hipError_t launch_interval(const KParams &p, bool fp32, int threads, int slots, int lds_bytes, hipStream_t st) {
-  IntervalFn fn = interval_fn(fp32, threads, slots);
+  (void)slots;
+  IntervalFn fn = interval_fn(fp32, threads);
   if (!fn) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(p.n_groups), dim3(threads), lds_bytes, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_fanout(const KParams &p, hipStream_t st) {
+  hipLaunchKernelGGL(cn_fanout, dim3(p.n_groups), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
