@@ -120,7 +120,8 @@ typedef struct cn_options {
   cn_alloc_fn dev_alloc;  /* optional */
   cn_free_fn dev_free;    /* required when dev_alloc is given */
   void *alloc_ctx;
-  int32_t event_capacity; /* events per cell group per interval (0: default 1024) */
+  int32_t event_capacity; /* events per cell group per interval, rounded up to a power of two (0: default 512);
+                             each group holds one interval's events on chip, so larger values cost occupancy */
   int32_t max_interval;   /* upper bound on steps per interval (0: default 64) */
   int32_t group_threads;  /* threads per cell group (0: auto) */
   int32_t use_graph;      /* 1: replay one captured hipGraph per interval; 0: direct launches */

@@ -562,11 +562,18 @@ static void build_tables(cn_model *m) {
   m->host_par = par;
   m->host_ch = ch;
   p.v = m->upload(std::vector<double>(N, m->v_init));
-  p.st_stride = N;
-  {
-    std::vector<double> all(6 * (size_t)N);
-    for (int k = 0; k < 6; ++k) std::copy(st[k].begin(), st[k].end(), all.begin() + (size_t)k * N);
-    p.st = m->upload_s(all);
+  p.v2 = static_cast<double *>(m->dalloc(N * sizeof(double)));
+  p.n_nodes_total = N;
+  if (m->fp32) {
+    std::vector<StRec<float>> r(N);
+    for (int64_t dn = 0; dn < N; ++dn)
+      r[dn] = StRec<float>{(float)st[0][dn], (float)st[1][dn], (float)st[2][dn], (float)st[3][dn], (float)st[4][dn],
+                           (float)st[5][dn]};
+    p.st = m->upload(r);
+  } else {
+    std::vector<StRec<double>> r(N);
+    for (int64_t dn = 0; dn < N; ++dn) r[dn] = StRec<double>{st[0][dn], st[1][dn], st[2][dn], st[3][dn], st[4][dn], st[5][dn]};
+    p.st = m->upload(r);
   }
   // density-mechanism parameters: scalars when every column is uniform, else a per-node table of all columns
   {
@@ -810,7 +817,7 @@ static void prepare_dt(cn_model *m, double dt) {
   }
   p.seed = m->seed;
   // event ring
-  int cap = m->opt.event_capacity > 0 ? m->opt.event_capacity : 1024;
+  int cap = m->opt.event_capacity > 0 ? m->opt.event_capacity : 512;
   int pc = 1;
   while (pc < cap) pc <<= 1;
   p.ev_cap = pc;
@@ -846,9 +853,9 @@ static void prepare_dt(cn_model *m, double dt) {
   p.rec_t = static_cast<double *>(m->dalloc(rc * sizeof(double)));
   p.ctl = static_cast<int64_t *>(m->dalloc(4 * sizeof(int64_t)));
   p.groups = m->upload(m->groups);
-  // LDS: five rows of doubles per node, event keys, step segments, level starts, background bits, counters
+  // LDS: four rows of doubles per node, event keys, step segments, level starts, background bits, counters
   p.nmax = m->nmax;
-  int off = 40 * m->nmax;
+  int off = 32 * m->nmax;
   p.lds_ev_off = off;
   off += p.ev_cap * 8;
   p.lds_seg_off = off;

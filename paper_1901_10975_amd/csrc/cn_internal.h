@@ -46,6 +46,11 @@ struct SynRec {
   S wbg;
   S f;
 };
+// channel states of one compartment (hh m, h, n; km n; cahi m, cai), double or float
+template <typename S>
+struct StRec {
+  S m, h, n, kn, cm, cai;
+};
 // IClamp record (device order): on for steps on <= n < off, current density 100 amp / area (mA/cm^2)
 struct IclRec {
   int64_t on, off;
@@ -81,10 +86,11 @@ struct KParams {
   const NodeRec *nrec;
   const NodeIdx *nidx;
   const int32_t *nd_icl0;  // group-local first IClamp of each node
-  double *v;
-  void *st;                // states: 6 arrays of st_stride elements (hh m, h, n; km n; cahi m, cai), double or float
-  int64_t st_stride;
-  const double *prm;       // N_PRM columns of st_stride values, or NULL when every column is uniform
+  double *v;               // membrane potential between chunks
+  double *v2;              // second buffer of the step-to-step double buffering
+  void *st;                // StRec<double> or StRec<float> per node
+  int64_t n_nodes_total;
+  const double *prm;       // N_PRM columns of n_nodes_total values, or NULL when every column is uniform
   double prm_s[N_PRM];     // the uniform values
   // synapses (device order)
   void *syn_g;             // double or float

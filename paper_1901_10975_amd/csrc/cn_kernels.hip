@@ -141,21 +141,69 @@ __device__ __forceinline__ uint32_t bg_mask4(uint64_t seed, uint64_t key, uint64
          ((uint64_t)c3 < thresh ? 8u : 0u);
 }
 
+// one node of the elimination: gather the children's contributions, then publish this node's own
+__device__ __forceinline__ void tri_node(int q, double a, double b, uint32_t ch, double *w_l, double *u_l, double *P_l,
+                                         double *Q_l) {
+  double d = w_l[q], rhs = u_l[q];
+  const int c0 = (int)(ch & 0xFFFFu), cn = (int)(ch >> 16);
+  for (int c = c0; c < c0 + cn; ++c) {
+    d -= P_l[c];
+    rhs -= Q_l[c];
+  }
+  const double ri = rcp64(d);
+  const double w = ri * b, u = ri * rhs;
+  w_l[q] = w;
+  u_l[q] = u;
+  P_l[q] = a * (w + 1.0);
+  Q_l[q] = a * (u - Q_l[q]);
+}
+
+struct SolveNode {
+  int q;
+  uint32_t ch;
+  double a, b;
+};
+
+// the node thread t handles at level L of the elimination (q >= the level's end when there is none)
+__device__ __forceinline__ SolveNode solve_node(const KParams &p, int64_t nb, const int *lv, int L, int t) {
+  SolveNode r{0x7FFFFFFF, 0u, 0.0, 0.0};
+  if (L >= 1) {
+    r.q = lv[L] + t;
+    if (r.q < lv[L + 1]) {
+      const NodeRec nr = p.nrec[nb + r.q];
+      r.a = nr.a;
+      r.b = nr.b;
+      r.ch = p.nidx[nb + r.q].ch;
+    }
+  }
+  return r;
+}
+
+// parent of the node thread t handles at level L of the substitution (0 when there is none)
+__device__ __forceinline__ int par_of(const KParams &p, int64_t nb, const int *lv, int D, int L, int t) {
+  if (L < D) {
+    const int q = lv[L] + t;
+    if (q < lv[L + 1]) return p.nidx[nb + q].par;
+  }
+  return 0;
+}
+
 // ------------------------------------------------------------------------------------------------------------------
-// LDS: five rows of nmax doubles per group -
-//   v_l  membrane potential;
+// LDS: four rows of nmax doubles per group -
 //   w_l  d (diagonal) after assembly, then w = b/d after elimination;
 //   u_l  rhs after assembly, then u = rhs/d after elimination;
-//   P_l  the node's contribution a(w + 1) to its parent's diagonal, later the solution x;
-//   Q_l  dv = v_parent - v after assembly, then the contribution a(u - dv) to the parent's rhs.
+//   P_l  the node's contribution a(w + 1) to its parent's diagonal, later the solution x = Delta v;
+//   Q_l  dv = v_parent - v after assembly (v itself at a root), then the contribution a(u - dv) to the parent's rhs.
 // With these, elimination of node i reads d_i, rhs_i and its children's contributions, and back-substitution is
 // x_i = u_i - w_i x_parent.
+// The membrane potential stays in global memory, double-buffered across steps: step k of a chunk reads v_{k-1}
+// from one buffer, adds the pending Delta v still held in P_l, and writes v_k to the other buffer, so a child reading
+// its parent's potential never races the parent's own update. The chunk's last Delta v is applied at its end.
 template <int T, typename S>
-__global__ void __launch_bounds__(T) cn_interval(const KParams p) {
+__global__ void __launch_bounds__(T, 4) cn_interval(const KParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int NMAX = p.nmax;
-  double *v_l = reinterpret_cast<double *>(lds);
-  double *w_l = v_l + NMAX;
+  double *w_l = reinterpret_cast<double *>(lds);
   double *u_l = w_l + NMAX;
   double *P_l = u_l + NMAX;
   double *Q_l = P_l + NMAX;
@@ -182,8 +230,7 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
   const int64_t nb = gd.node_base;
   const int64_t sb = gd.syn_base;
 
-  // ---- prologue: voltages and level starts on chip, this interval's events sorted
-  for (int q = t; q < N; q += T) v_l[q] = p.v[nb + q];
+  // ---- prologue: level starts on chip, this interval's events sorted
   for (int L = t; L <= D; L += T) lv[L] = p.lvl_start[gd.lvl_base + L];
   if (t < N_PRM) cst[C_PRM + t] = p.prm_s[t];
   if (t == 0) {
@@ -265,10 +312,11 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
   }
   __syncthreads();
 
-  S *st = static_cast<S *>(p.st);
+  StRec<S> *st = static_cast<StRec<S> *>(p.st);
+  const int64_t sst = p.n_nodes_total;
   const SynRec<S> *syn = static_cast<const SynRec<S> *>(p.syn) + sb;
-  const int64_t sst = p.st_stride;
   S *sg = static_cast<S *>(p.syn_g) + sb;
+  double *const vbuf[2] = {p.v2 + nb, p.v + nb};  // step k writes vbuf[k & 1]; p.v holds v between chunks
   const int lv1 = lv[1];
   if (!p.has_bg)
     for (int i = t; i < n_syn; i += T) bgm[i] = 0;
@@ -299,31 +347,58 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
     // ---- C: states, currents, conductances and the compartment's own axial terms
     const bool pend = n > 0;
     const uint32_t bsh = (uint32_t)(n & 3);
+    const int kk = (int)(n - n_begin);
+    const bool first = kk == 0;
+    const double *vr = first ? p.v + nb : vbuf[(kk - 1) & 1];  // v_{k-1} (pending Delta v in P_l unless first)
+    double *vw = vbuf[kk & 1];
     const S q10dt = (S)cst[C_Q10DT];
     const S sdt = (S)cst[C_DT];
     const S ca_fm = (S)cst[C_CA_FM], ca_fr = (S)cst[C_CA_FR], ca_k = (S)cst[C_CA_K];
+    // records and states of the thread's next compartment are loaded while the current one is computed
+    NodeRec nr_n{};
+    NodeIdx nx_n{};
+    StRec<S> sr_n{};
+    double v_n = 0.0;
+    if (t < N) {
+      nr_n = p.nrec[nb + t];
+      nx_n = p.nidx[nb + t];
+      sr_n = st[nb + t];
+      v_n = vr[t];
+    }
 #pragma unroll 1
     for (int q = t; q < N; q += T) {
       const int64_t i = nb + q;
-      const NodeRec nr = p.nrec[i];
-      const NodeIdx nx = p.nidx[i];
-      const double v = v_l[q];
+      const NodeRec nr = nr_n;
+      const NodeIdx nx = nx_n;
+      StRec<S> sr = sr_n;
+      const double vpar_old = nx.par >= 0 ? vr[nx.par] : 0.0;
+      const double v = first ? v_n : v_n + P_l[q];
+      if (q + T < N) {
+        nr_n = p.nrec[i + T];
+        nx_n = p.nidx[i + T];
+        sr_n = st[i + T];
+        v_n = vr[q + T];
+      }
+      vw[q] = v;
       double rhs = 0.0, d = 0.0;
       const uint32_t mf = nx.pk >> 24;
-      if (mf & MF_HH) {
-        S m = st[i], h = st[sst + i], nn = st[2 * sst + i];
-        if (pend) {
-          hh_advance<S>(v, q10dt, m, h, nn);
-          st[i] = m;
-          st[sst + i] = h;
-          st[2 * sst + i] = nn;
+      const bool has_st = (mf & (MF_HH | MF_KM | MF_CAHI)) != 0;
+      if (pend && has_st) {
+        if (mf & MF_HH) hh_advance<S>(v, q10dt, sr.m, sr.h, sr.n);
+        if (mf & MF_KM) km_advance<S>(v, sdt, sr.kn);
+        if (mf & MF_CAHI) {
+          const S gca = (S)(p.prm ? p.prm[P_CA_G * sst + i] : cst[C_PRM + P_CA_G]);
+          cahi_advance<S>(v, ca_fm, ca_fr, ca_k, gca, sr.cm, sr.cai);
         }
+        st[i] = sr;
+      }
+      if (mf & MF_HH) {
         const double gnab = p.prm ? p.prm[P_HH_GNA * sst + i] : cst[C_PRM + P_HH_GNA];
         const double gkb = p.prm ? p.prm[P_HH_GK * sst + i] : cst[C_PRM + P_HH_GK];
         const double gl = p.prm ? p.prm[P_HH_GL * sst + i] : cst[C_PRM + P_HH_GL];
         const double el = p.prm ? p.prm[P_HH_EL * sst + i] : cst[C_PRM + P_HH_EL];
-        const double gna = (double)((S)gnab * (m * m * m * h));
-        const double gk = (double)((S)gkb * ((nn * nn) * (nn * nn)));
+        const double gna = (double)((S)gnab * (sr.m * sr.m * sr.m * sr.h));
+        const double gk = (double)((S)gkb * ((sr.n * sr.n) * (sr.n * sr.n)));
         rhs -= gna * (v - 50.0) + gk * (v + 77.0) + gl * (v - el);
         d += gna + gk + gl;
       }
@@ -334,25 +409,13 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
         d += g;
       }
       if (mf & MF_KM) {
-        S nk = st[3 * sst + i];
-        if (pend) {
-          km_advance<S>(v, sdt, nk);
-          st[3 * sst + i] = nk;
-        }
-        const double g = (double)((S)(p.prm ? p.prm[P_KM_G * sst + i] : cst[C_PRM + P_KM_G]) * nk);
+        const double g = (double)((S)(p.prm ? p.prm[P_KM_G * sst + i] : cst[C_PRM + P_KM_G]) * sr.kn);
         rhs -= g * (v + 77.0);
         d += g;
       }
       if (mf & MF_CAHI) {
         const S gca = (S)(p.prm ? p.prm[P_CA_G * sst + i] : cst[C_PRM + P_CA_G]);
-        S mc = st[4 * sst + i];
-        if (pend) {
-          S cai = st[5 * sst + i];
-          cahi_advance<S>(v, ca_fm, ca_fr, ca_k, gca, mc, cai);
-          st[4 * sst + i] = mc;
-          st[5 * sst + i] = cai;
-        }
-        const double g = (double)(gca * (mc * mc));
+        const double g = (double)(gca * (sr.cm * sr.cm));
         rhs -= g * (v - 120.0);
         d += g;
       }
@@ -374,73 +437,45 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
         sg[ls] = g * sr.f;  // decay of this step, applied ahead of the next delivery
       }
       d += nr.k;
-      double dv = 0.0;
+      double dvq = v;  // a root keeps its own potential here for threshold detection
       if (nx.par >= 0) {
-        dv = v_l[nx.par] - v;
+        const double vpar = first ? vpar_old : vpar_old + P_l[nx.par];
+        const double dv = vpar - v;
         rhs -= nr.b * dv;
+        dvq = dv;
       }
       w_l[q] = d;
       u_l[q] = rhs;
-      Q_l[q] = dv;
+      Q_l[q] = dvq;
     }
     __syncthreads();
-    // ---- T: elimination, deepest level first, one thread per node of the level. Node records of the next
-    // (shallower) level are fetched while the current one is processed.
-    int Lc = D - 1;
-    int qn = Lc >= 1 ? lv[Lc] + t : NMAX;
-    NodeRec rn{};
-    uint32_t chn = 0;
-    if (Lc >= 1 && qn < lv[Lc + 1]) {
-      rn = p.nrec[nb + qn];
-      chn = p.nidx[nb + qn].ch;
-    }
-    for (; Lc >= 1; --Lc) {
-      const int lo = lv[Lc], hi = lv[Lc + 1];
-      const NodeRec r = rn;
-      const uint32_t ch = chn;
-      const int q = qn;
-      if (Lc >= 2) {
-        qn = lv[Lc - 1] + t;
-        if (qn < lo) {
-          rn = p.nrec[nb + qn];
-          chn = p.nidx[nb + qn].ch;
+    // ---- T: elimination, deepest level first, one thread per node of the level. Each thread's node records for
+    // the next three levels are in flight while the current level is processed (they are loop invariant, but
+    // too many to keep on chip for the whole chunk).
+    const uint32_t root_ch = t < lv1 ? p.nidx[nb + t].ch : 0u;  // roots' children, used after the elimination
+    {
+      SolveNode c0n, c1n, c2n;
+      int Lc = D - 1;
+      c0n = solve_node(p, nb, lv, Lc, t);
+      c1n = solve_node(p, nb, lv, Lc - 1, t);
+      c2n = solve_node(p, nb, lv, Lc - 2, t);
+      for (; Lc >= 1; --Lc) {
+        const SolveNode cur = c0n;
+        c0n = c1n;
+        c1n = c2n;
+        c2n = solve_node(p, nb, lv, Lc - 3, t);
+        const int q = lv[Lc] + t, hi = lv[Lc + 1];
+        if (q < hi) tri_node(q, cur.a, cur.b, cur.ch, w_l, u_l, P_l, Q_l);
+        for (int q2 = q + T; q2 < hi; q2 += T) {  // levels wider than the group's threads
+          const NodeRec r2 = p.nrec[nb + q2];
+          tri_node(q2, r2.a, r2.b, p.nidx[nb + q2].ch, w_l, u_l, P_l, Q_l);
         }
+        __syncthreads();
       }
-      if (q < hi) {
-        double d = w_l[q], rhs = u_l[q];
-        const int c0 = (int)(ch & 0xFFFFu), cn = (int)(ch >> 16);
-        for (int c = c0; c < c0 + cn; ++c) {
-          d -= P_l[c];
-          rhs -= Q_l[c];
-        }
-        const double ri = rcp64(d);
-        const double w = ri * r.b, u = ri * rhs;
-        w_l[q] = w;
-        u_l[q] = u;
-        P_l[q] = r.a * (w + 1.0);
-        Q_l[q] = r.a * (u - Q_l[q]);
-      }
-      for (int q2 = q + T; q2 < hi; q2 += T) {  // levels wider than the group's threads
-        const NodeRec r2 = p.nrec[nb + q2];
-        const uint32_t ch2 = p.nidx[nb + q2].ch;
-        double d = w_l[q2], rhs = u_l[q2];
-        const int c0 = (int)(ch2 & 0xFFFFu), cn = (int)(ch2 >> 16);
-        for (int c = c0; c < c0 + cn; ++c) {
-          d -= P_l[c];
-          rhs -= Q_l[c];
-        }
-        const double ri = rcp64(d);
-        const double w = ri * r2.b, u = ri * rhs;
-        w_l[q2] = w;
-        u_l[q2] = u;
-        P_l[q2] = r2.a * (w + 1.0);
-        Q_l[q2] = r2.a * (u - Q_l[q2]);
-      }
-      __syncthreads();
     }
     // ---- R: roots (level 0 holds the group's cells in order): solve, v update, threshold detection
     for (int q = t; q < lv1; q += T) {
-      const uint32_t ch = p.nidx[nb + q].ch;
+      const uint32_t ch = q == t ? root_ch : p.nidx[nb + q].ch;
       double d = w_l[q], rhs = u_l[q];
       const int c0 = (int)(ch & 0xFFFFu), cn = (int)(ch >> 16);
       for (int c = c0; c < c0 + cn; ++c) {
@@ -448,9 +483,8 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
         rhs -= Q_l[c];
       }
       const double x = rhs / d;
-      const double vold = v_l[q];
+      const double vold = Q_l[q];
       const double vnew = vold + x;
-      v_l[q] = vnew;
       P_l[q] = x;
       const double th = p.cell_theta[gd.cell_base + q];
       if (vold < th && th <= vnew) {
@@ -461,34 +495,34 @@ __global__ void __launch_bounds__(T) cn_interval(const KParams p) {
       if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
     }
     __syncthreads();
-    // ---- B: substitution, root to leaves: x = u - w x_parent (parents of the next level fetched ahead)
+    // ---- B: substitution, root to leaves: x = u - w x_parent (parents of the next three levels in flight)
     {
-      int qb = D > 1 ? lv[1] + t : NMAX;
-      int parn = (D > 1 && qb < lv[2]) ? p.nidx[nb + qb].par : 0;
+      int p0 = par_of(p, nb, lv, D, 1, t), p1 = par_of(p, nb, lv, D, 2, t), p2 = par_of(p, nb, lv, D, 3, t);
       for (int L = 1; L < D; ++L) {
         const int lo = lv[L], hi = lv[L + 1];
-        const int q = qb, par = parn;
-        if (L + 1 < D) {
-          qb = hi + t;
-          if (qb < lv[L + 2]) parn = p.nidx[nb + qb].par;
-        }
+        const int q = lo + t, par = p0;
+        p0 = p1;
+        p1 = p2;
+        p2 = par_of(p, nb, lv, D, L + 3, t);
         if (q < hi) {
           const double x = u_l[q] - w_l[q] * P_l[par];
           P_l[q] = x;
-          v_l[q] += x;
         }
         for (int q2 = q + T; q2 < hi; q2 += T) {
           const double x = u_l[q2] - w_l[q2] * P_l[p.nidx[nb + q2].par];
           P_l[q2] = x;
-          v_l[q2] += x;
         }
         __syncthreads();
       }
     }
   }
 
-  // ---- epilogue: write back; the chunk's spikes (count in gsp_cnt) are recorded and fanned out by cn_fanout
-  for (int q = t; q < N; q += T) p.v[nb + q] = v_l[q];
+  // ---- epilogue: apply the last step's Delta v; the chunk's spikes (count in gsp_cnt) are recorded and fanned
+  // out by cn_fanout
+  {
+    const double *vl = vbuf[(int)(n_end - 1 - n_begin) & 1];
+    for (int q = t; q < N; q += T) p.v[nb + q] = vl[q] + P_l[q];
+  }
   if (t == 0) {
     p.gsp_cnt[G] = misc[1];
     if (n_end == (ival + 1) * (int64_t)M) p.ev_cnt[(int64_t)slot * p.n_groups + G] = 0;
@@ -572,21 +606,18 @@ __global__ void cn_read_state(const KParams p, int64_t n_nodes, int64_t step, in
   if (i >= n_nodes) return;
   const double v = p.v[i];
   const bool pend = step > 0;
-  const S *st = static_cast<const S *>(p.st);
-  const int64_t sst = p.st_stride;
+  StRec<S> sr = static_cast<const StRec<S> *>(p.st)[i];
+  const int64_t sst = p.n_nodes_total;
   if (type == 0) {
-    S m = st[i], h = st[sst + i], nn = st[2 * sst + i];
-    if (pend) hh_advance<S>(v, (S)p.q10dt, m, h, nn);
-    out[i] = which == 0 ? (double)m : (which == 1 ? (double)h : (double)nn);
+    if (pend) hh_advance<S>(v, (S)p.q10dt, sr.m, sr.h, sr.n);
+    out[i] = which == 0 ? (double)sr.m : (which == 1 ? (double)sr.h : (double)sr.n);
   } else if (type == 2) {
-    S nk = st[3 * sst + i];
-    if (pend) km_advance<S>(v, (S)p.dt, nk);
-    out[i] = (double)nk;
+    if (pend) km_advance<S>(v, (S)p.dt, sr.kn);
+    out[i] = (double)sr.kn;
   } else if (type == 3) {
-    S mc = st[4 * sst + i], cai = st[5 * sst + i];
     const S gca = (S)(p.prm ? p.prm[P_CA_G * sst + i] : p.prm_s[P_CA_G]);
-    if (pend) cahi_advance<S>(v, (S)p.ca_fm, (S)p.ca_fr, (S)p.ca_k, gca, mc, cai);
-    out[i] = which == 0 ? (double)mc : (double)cai;
+    if (pend) cahi_advance<S>(v, (S)p.ca_fm, (S)p.ca_fr, (S)p.ca_k, gca, sr.cm, sr.cai);
+    out[i] = which == 0 ? (double)sr.cm : (double)sr.cai;
   }
 }
 
