@@ -22,7 +22,8 @@
 
 namespace cn {
 hipError_t launch_interval(const KParams &p, bool fp32, int threads, int slots, int lds_bytes, hipStream_t st);
-hipError_t set_interval_lds(bool fp32, int threads, int slots, int lds_bytes);
+hipError_t set_interval_lds(bool fp32, int threads, int slots, bool uni, int lds_bytes);
+int interval_node_bytes(int nmax);
 hipError_t launch_advance(int64_t *ctl, int32_t M, hipStream_t st);
 hipError_t launch_fanout(const KParams &p, hipStream_t st);
 hipError_t launch_set_ctl(int64_t *ctl, int64_t n_begin, int64_t n_target, hipStream_t st);
@@ -124,6 +125,7 @@ struct cn_model {
   std::vector<uint32_t> host_ch;
   std::vector<uint64_t> host_syn_key;
   std::vector<double> host_syn_e, host_syn_wbg;
+  std::vector<int32_t> host_syn_q;
   int32_t max_levels = 0, max_group_syn = 0, max_group_nodes = 0;
 
   // ---- device
@@ -313,11 +315,13 @@ void build_layout(cn_model *m) {
   const Table &syn = m->mech[CN_MECH_EXPSYN];
   for (int64_t k = 0; k < syn.n; ++k) syn_per_cell[cell_of[syn.node[k]]]++;
 
-  // group shape: T threads x K register slots, capacity T*K nodes
-  int T = m->opt.group_threads > 0 ? m->opt.group_threads : 256;
+  // group shape: T threads x K register slots per thread, capacity T*K compartments. Shapes compiled:
+  // T = 128 with K = 2, 4, 8; T = 256 with K = 1, 2, 4; T = 512 with K = 2, 4, 8.
+  int T = m->opt.group_threads;
+  if (T == 0) T = max_cell <= 1024 ? 256 : 512;
   if (T != 128 && T != 256 && T != 512) throw Err{CN_E_INVALID, "group_threads must be 128, 256 or 512"};
-  const int kmax = T == 512 ? 4 : 8;
-  int K = 1;
+  const int kmin = T == 256 ? 1 : 2, kmax = T == 256 ? 4 : 8;
+  int K = kmin;
   while (K < kmax && T * K < max_cell) K *= 2;
   if (T * K < max_cell) throw Err{CN_E_INVALID, "a cell has more compartments (" + std::to_string(max_cell) +
                                                    ") than one cell group holds (" + std::to_string(T * K) + ")"};
@@ -325,7 +329,8 @@ void build_layout(cn_model *m) {
   m->threads = T;
   m->slots = K;
   m->nmax = T * K;
-  const int64_t syn_cap = 4096;
+  // synapses per group: up to two LDS rows, so that their terms can be staged on chip
+  const int64_t syn_cap = 2 * m->nmax;
 
   // best-fit decreasing on compartments, with a synapse cap per group
   std::vector<int32_t> order(m->n_cells);
@@ -562,7 +567,11 @@ static void build_tables(cn_model *m) {
   m->host_par = par;
   m->host_ch = ch;
   p.v = m->upload(std::vector<double>(N, m->v_init));
-  p.v2 = static_cast<double *>(m->dalloc(N * sizeof(double)));
+  {
+    std::vector<double> et(64);
+    for (int j = 0; j < 64; ++j) et[j] = (double)exp2l((long double)j / 64.0L);
+    p.exp_tab = m->upload(et);
+  }
   p.n_nodes_total = N;
   if (m->fp32) {
     std::vector<StRec<float>> r(N);
@@ -618,6 +627,7 @@ static void build_tables(cn_model *m) {
   // group bases and per-node ranges
   {
     int64_t sd = 0, id = 0;
+    m->host_syn_q.assign(syn.n, 0);
     for (int64_t g = 0; g < m->n_groups; ++g) {
       GroupDesc &gd = m->groups[g];
       gd.syn_base = sd;
@@ -628,6 +638,7 @@ static void build_tables(cn_model *m) {
         const int64_t dn = m->dev_of_node[syn.node[m->syn_of_dev[sd]]];
         if (nd_syn[dn].y == 0) nd_syn[dn].x = (int)(sd - s0);
         nd_syn[dn].y++;
+        m->host_syn_q[sd] = (int32_t)(dn - gd.node_base);
         ++sd;
       }
       while (id < icl.n && m->dev_of_node[icl.node[m->icl_of_dev[id]]] < end) {
@@ -766,17 +777,22 @@ static void prepare_dt(cn_model *m, double dt) {
   }
   const Table &syn = m->mech[CN_MECH_EXPSYN];
   {
-    // synapse records: stream id, reversal, background weight, decay factor exp(-dt/tau)
+    // synapse records: stream id, reversal, 100/area of the compartment, background weight, decay factor
+    // exp(-dt/tau), compartment
     std::vector<double> f(syn.n);
+    auto syn_sa = [&](int64_t d) { return m->host_sa[m->dev_of_node[syn.node[m->syn_of_dev[d]]]]; };
     for (int64_t d = 0; d < syn.n; ++d) f[d] = std::exp(-dt / syn.p[0].v[m->syn_of_dev[d]]);
     if (m->fp32) {
       std::vector<SynRec<float>> r(syn.n);
       for (int64_t d = 0; d < syn.n; ++d)
-        r[d] = SynRec<float>{m->host_syn_key[d], m->host_syn_e[d], (float)m->host_syn_wbg[d], (float)f[d]};
+        r[d] = SynRec<float>{m->host_syn_key[d], m->host_syn_e[d], syn_sa(d), (float)m->host_syn_wbg[d], (float)f[d],
+                             m->host_syn_q[d], 0};
       p.syn = m->upload(r);
     } else {
       std::vector<SynRec<double>> r(syn.n);
-      for (int64_t d = 0; d < syn.n; ++d) r[d] = SynRec<double>{m->host_syn_key[d], m->host_syn_e[d], m->host_syn_wbg[d], f[d]};
+      for (int64_t d = 0; d < syn.n; ++d)
+        r[d] = SynRec<double>{m->host_syn_key[d], m->host_syn_e[d], syn_sa(d), m->host_syn_wbg[d], f[d],
+                              m->host_syn_q[d], 0};
       p.syn = m->upload(r);
     }
   }
@@ -853,9 +869,11 @@ static void prepare_dt(cn_model *m, double dt) {
   p.rec_t = static_cast<double *>(m->dalloc(rc * sizeof(double)));
   p.ctl = static_cast<int64_t *>(m->dalloc(4 * sizeof(int64_t)));
   p.groups = m->upload(m->groups);
-  // LDS: four rows of doubles per node, event keys, step segments, level starts, background bits, counters
+  // LDS: four working rows of doubles per node (the kernel sizes rows by the group capacity T K), the per-node
+  // constants (three doubles and three 32-bit indices) for groups of up to 2048 nodes, event keys, step segments,
+  // level starts, background bits, counters
   p.nmax = m->nmax;
-  int off = 32 * m->nmax;
+  int off = interval_node_bytes(m->nmax) * m->nmax;
   p.lds_ev_off = off;
   off += p.ev_cap * 8;
   p.lds_seg_off = off;
@@ -869,11 +887,13 @@ static void prepare_dt(cn_model *m, double dt) {
   off += 16;
   p.lds_cst_off = off;
   off += N_CST * 8;
+  p.lds_exp_off = off;
+  off += 64 * 8;
   m->lds_bytes = off;
   if (m->lds_bytes > 160 * 1024)
     throw Err{CN_E_INVALID, "cell groups need " + std::to_string(m->lds_bytes) + " bytes of LDS (event_capacity "
                                 "or synapses per group too large)"};
-  HIPCHK(set_interval_lds(m->fp32, m->threads, m->slots, m->lds_bytes));
+  HIPCHK(set_interval_lds(m->fp32, m->threads, m->slots, p.prm == nullptr, m->lds_bytes));
   HIPCHK(hipStreamSynchronize(m->stream));
   if (m->opt.use_graph) {
     HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));

@@ -4,7 +4,8 @@
 // interval (cells do not interact inside an interval, Sec. 2). Inside a group the compartments are stored level by
 // level (all roots, then all depth-1 nodes, ...), children of one parent contiguous and in ascending cell-local
 // index: the constant-depth ordering of Sec. 4.4, which here lets each level of the tree elimination run in
-// parallel, one thread per node of the level.
+// parallel, one thread per node of the level. Node q of a group sits in register slot q / T of thread q % T for the
+// per-compartment work (mechanisms and assembly).
 #pragma once
 #include <stdint.h>
 
@@ -38,13 +39,17 @@ struct NodeIdx {
   uint32_t pk;
 };
 
-// synapse record (device order): background stream id, reversal potential, background weight and decay factor
+// synapse record (device order): background stream id, reversal potential, 100/area of its compartment, background
+// weight, decay factor, and its compartment (group-local node)
 template <typename S>
 struct SynRec {
   uint64_t key;
   double e;
+  double sa;
   S wbg;
   S f;
+  int32_t q;
+  int32_t pad;
 };
 // channel states of one compartment (hh m, h, n; km n; cahi m, cai), double or float
 template <typename S>
@@ -81,13 +86,13 @@ struct KParams {
   int32_t ev_cap;
   int32_t nmax;  // nodes per group (LDS rows)
   int32_t has_bg;
-  int32_t lds_ev_off, lds_seg_off, lds_lvl_off, lds_bg_off, lds_misc_off, lds_cst_off;
+  int32_t lds_ev_off, lds_seg_off, lds_lvl_off, lds_bg_off, lds_misc_off, lds_cst_off, lds_exp_off;
+  const double *exp_tab;   // 2^(j/64), j = 0..63
   // node tables (device order)
   const NodeRec *nrec;
   const NodeIdx *nidx;
   const int32_t *nd_icl0;  // group-local first IClamp of each node
   double *v;               // membrane potential between chunks
-  double *v2;              // second buffer of the step-to-step double buffering
   void *st;                // StRec<double> or StRec<float> per node
   int64_t n_nodes_total;
   const double *prm;       // N_PRM columns of n_nodes_total values, or NULL when every column is uniform

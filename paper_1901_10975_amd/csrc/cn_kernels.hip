@@ -32,9 +32,25 @@ namespace cn {
 // exponentials in float with the hardware exp; voltage, currents, assembly and solve stay double).
 template <typename S>
 struct Math;
+// the exp table lives in LDS; the explicit address space keeps its loads LDS reads after inlining
+typedef const __attribute__((address_space(3))) double lds_table;
+// exp in double by Tang's table-driven method (ACM TOMS 15(2), 1989): x = (64 m + j) ln2/64 + r with |r| <= ln2/128,
+// exp(x) = 2^m 2^(j/64) exp(r), exp(r) - 1 by its Taylor series to r^5 (truncation below 4e-17 relative). The 64
+// table values 2^(j/64) sit in LDS (exp_tab). Arguments here are bounded (|x| < 60); no overflow handling.
+__device__ __forceinline__ double exp_tang(double x, const lds_table *exp_tab) {
+  const double n = __builtin_rint(x * 92.33248261689366);  // 64 / ln 2
+  const int ni = (int)n;
+  // ln2/64 = hi + lo, hi with its low 12 mantissa bits clear so that n hi is exact
+  const double r = fma(-n, 4.411764150473684e-15, fma(-n, 0.010830424696244734, x));
+  const double c = fma(fma(fma(r, 1.0 / 120.0, 1.0 / 24.0), r, 1.0 / 6.0), r, 0.5);
+  const double pr = fma(r * r, c, r);  // exp(r) - 1
+  const double tj = exp_tab[ni & 63];
+  return __builtin_ldexp(fma(tj, pr, tj), ni >> 6);
+}
+
 template <>
 struct Math<double> {
-  static __device__ __forceinline__ double ex(double x) { return exp(x); }
+  static __device__ __forceinline__ double ex(double x, const lds_table *et) { return exp_tang(x, et); }
   // reciprocal: hardware estimate refined by two Newton steps (error within an ulp or two of 1/x)
   static __device__ __forceinline__ double rcp(double x) {
     double r = __builtin_amdgcn_rcp(x);
@@ -44,14 +60,14 @@ struct Math<double> {
     return fma(r, e, r);
   }
   // 1 - exp(-z)
-  static __device__ __forceinline__ double omx(double z) { return 1.0 - exp(-z); }
+  static __device__ __forceinline__ double omx(double z, const lds_table *et) { return 1.0 - exp_tang(-z, et); }
 };
 template <>
 struct Math<float> {
-  static __device__ __forceinline__ float ex(float x) { return __expf(x); }
+  static __device__ __forceinline__ float ex(float x, const lds_table *) { return __expf(x); }
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
   // 1 - exp(-z) without the cancellation of the subtraction at small z (four-term series below 0.03)
-  static __device__ __forceinline__ float omx(float z) {
+  static __device__ __forceinline__ float omx(float z, const lds_table *) {
     return z < 0.03f ? z * (1.0f - z * 0.5f * (1.0f - z * (1.0f / 3.0f) * (1.0f - 0.25f * z))) : 1.0f - __expf(-z);
   }
 };
@@ -63,48 +79,53 @@ constexpr double E_POS_0P5 = 1.64872127070012814685;  // exp(0.5)
 
 // Hodgkin-Huxley gates, exponential relaxation toward x_inf(v) over dt with v frozen.
 template <typename S>
-__device__ __forceinline__ void hh_advance(double vd, S q10dt, S &m, S &h, S &n) {
+__device__ __forceinline__ void hh_advance(double vd, S q10dt, S &m, S &h, S &n, const lds_table *et) {
   using M = Math<S>;
   const S v = (S)vd;
   const S u = v + S(40);
   const S xm = -u * S(0.1);  // -(v+40)/10
-  const S e40 = M::ex(xm);
-  const S am = fabs(xm) < S(1e-6) ? S(1) * (S(1) - xm * S(0.5)) : S(0.1) * (-u) * M::rcp(e40 - S(1));
+  const S e40 = M::ex(xm, et);
+  // vtrap(x, y) = x / (exp(x/y) - 1), and its series y (1 - x/y/2) when |x/y| < 1e-6 (selected without a branch)
+  const S am_s = S(1) * (S(1) - xm * S(0.5));
+  const S am_e = S(0.1) * (-u) * M::rcp(e40 - S(1));
+  const S am = fabs(xm) < S(1e-6) ? am_s : am_e;
   const S xn = xm - S(1.5);  // -(v+55)/10
   const S en = e40 * S(E_NEG_1P5);
-  const S an = fabs(xn) < S(1e-6) ? S(0.1) * (S(1) - xn * S(0.5)) : S(0.01) * (-(u + S(15))) * M::rcp(en - S(1));
+  const S an_s = S(0.1) * (S(1) - xn * S(0.5));
+  const S an_e = S(0.01) * (-(u + S(15))) * M::rcp(en - S(1));
+  const S an = fabs(xn) < S(1e-6) ? an_s : an_e;
   const S bh = M::rcp(e40 * S(E_POS_0P5) + S(1));
   const S w = v + S(65);
-  const S bm = S(4) * M::ex(w * S(-1.0 / 18.0));
-  const S e80 = M::ex(w * S(-1.0 / 80.0));
+  const S bm = S(4) * M::ex(w * S(-1.0 / 18.0), et);
+  const S e80 = M::ex(w * S(-1.0 / 80.0), et);
   const S e20 = (e80 * e80) * (e80 * e80);
   const S ah = S(0.07) * e20;
   const S bn = S(0.125) * e80;
   const S sm = am + bm, sh = ah + bh, sn = an + bn;
-  m += M::omx(q10dt * sm) * (am * M::rcp(sm) - m);
-  h += M::omx(q10dt * sh) * (ah * M::rcp(sh) - h);
-  n += M::omx(q10dt * sn) * (an * M::rcp(sn) - n);
+  m += M::omx(q10dt * sm, et) * (am * M::rcp(sm) - m);
+  h += M::omx(q10dt * sh, et) * (ah * M::rcp(sh) - h);
+  n += M::omx(q10dt * sn, et) * (an * M::rcp(sn) - n);
 }
 
 // slow K: n_inf = 1/(1+exp(-(v+35)/10)), tau = 400/(3.3 exp((v+35)/20) + exp(-(v+35)/20)) ms
 template <typename S>
-__device__ __forceinline__ void km_advance(double vd, S dt, S &n) {
+__device__ __forceinline__ void km_advance(double vd, S dt, S &n, const lds_table *et) {
   using M = Math<S>;
   const S u = (S)vd + S(35);
-  const S e = M::ex(u * S(0.05));
+  const S e = M::ex(u * S(0.05), et);
   const S ei = M::rcp(e);
   const S ninf = M::rcp(S(1) + ei * ei);
   const S z = dt * S(1.0 / 400.0) * (S(3.3) * e + ei);
-  n += M::omx(z) * (ninf - n);
+  n += M::omx(z, et) * (ninf - n);
 }
 
 // high-threshold Ca: m_inf = 1/(1+exp(-(v+20)/9)), tau_m 1 ms; shell calcium relaxing toward
 // cai0 - k tau_r ica with ica taken at the new m.
 template <typename S>
-__device__ __forceinline__ void cahi_advance(double vd, S fm, S fr, S kk, S gca, S &m, S &cai) {
+__device__ __forceinline__ void cahi_advance(double vd, S fm, S fr, S kk, S gca, S &m, S &cai, const lds_table *et) {
   using M = Math<S>;
   const S v = (S)vd;
-  const S minf = M::rcp(S(1) + M::ex((v + S(20)) * S(-1.0 / 9.0)));
+  const S minf = M::rcp(S(1) + M::ex((v + S(20)) * S(-1.0 / 9.0), et));
   m += fm * (minf - m);
   const S ica = gca * m * m * (v - S(120));
   cai += fr * (S(5e-5) - kk * ica - cai);
@@ -141,78 +162,96 @@ __device__ __forceinline__ uint32_t bg_mask4(uint64_t seed, uint64_t key, uint64
          ((uint64_t)c3 < thresh ? 8u : 0u);
 }
 
-// one node of the elimination: gather the children's contributions, then publish this node's own
-__device__ __forceinline__ void tri_node(int q, double a, double b, uint32_t ch, double *w_l, double *u_l, double *P_l,
-                                         double *Q_l) {
-  double d = w_l[q], rhs = u_l[q];
-  const int c0 = (int)(ch & 0xFFFFu), cn = (int)(ch >> 16);
-  for (int c = c0; c < c0 + cn; ++c) {
-    d -= P_l[c];
-    rhs -= Q_l[c];
-  }
-  const double ri = rcp64(d);
-  const double w = ri * b, u = ri * rhs;
-  w_l[q] = w;
-  u_l[q] = u;
-  P_l[q] = a * (w + 1.0);
-  Q_l[q] = a * (u - Q_l[q]);
-}
-
-struct SolveNode {
-  int q;
+// a node's own inputs to the elimination: a, b, children, and from the assembly d, rhs and dv (v at a root)
+struct TriIn {
+  double a, b, d, r, dv;
   uint32_t ch;
-  double a, b;
 };
 
-// the node thread t handles at level L of the elimination (q >= the level's end when there is none)
-__device__ __forceinline__ SolveNode solve_node(const KParams &p, int64_t nb, const int *lv, int L, int t) {
-  SolveNode r{0x7FFFFFFF, 0u, 0.0, 0.0};
-  if (L >= 1) {
-    r.q = lv[L] + t;
-    if (r.q < lv[L + 1]) {
-      const NodeRec nr = p.nrec[nb + r.q];
-      r.a = nr.a;
-      r.b = nr.b;
-      r.ch = p.nidx[nb + r.q].ch;
+// subtract the children's contributions (children c0 .. c0 + count - 1 on the level below) from d and rhs, in child
+// order; the loads are issued four children at a time so that one LDS round trip serves most nodes
+__device__ __forceinline__ void gather_children(uint32_t ch, const double *P_l, const double *Q_l, double &d,
+                                                double &rhs) {
+  const int c0 = (int)(ch & 0xFFFFu), ce = c0 + (int)(ch >> 16);
+  for (int c = c0; c < ce; c += 4) {
+    const int c1 = min(c + 1, ce - 1), c2 = min(c + 2, ce - 1), c3 = min(c + 3, ce - 1);
+    const double p0 = P_l[c], p1 = P_l[c1], p2 = P_l[c2], p3 = P_l[c3];
+    const double q0 = Q_l[c], q1 = Q_l[c1], q2 = Q_l[c2], q3 = Q_l[c3];
+    d -= p0;
+    rhs -= q0;
+    if (c + 1 < ce) {
+      d -= p1;
+      rhs -= q1;
+    }
+    if (c + 2 < ce) {
+      d -= p2;
+      rhs -= q2;
+    }
+    if (c + 3 < ce) {
+      d -= p3;
+      rhs -= q3;
     }
   }
-  return r;
 }
 
-// parent of the node thread t handles at level L of the substitution (0 when there is none)
-__device__ __forceinline__ int par_of(const KParams &p, int64_t nb, const int *lv, int D, int L, int t) {
-  if (L < D) {
-    const int q = lv[L] + t;
-    if (q < lv[L + 1]) return p.nidx[nb + q].par;
-  }
-  return 0;
+// one node of the elimination: gather the children's contributions, then publish this node's own
+__device__ __forceinline__ void tri_node(int q, const TriIn &x, double *w_l, double *u_l, double *P_l, double *Q_l) {
+  double d = x.d, rhs = x.r;
+  gather_children(x.ch, P_l, Q_l, d, rhs);
+  const double ri = rcp64(d);
+  const double w = ri * x.b, u = ri * rhs;
+  w_l[q] = w;
+  u_l[q] = u;
+  P_l[q] = x.a * (w + 1.0);
+  Q_l[q] = x.a * (u - x.dv);
 }
 
 // ------------------------------------------------------------------------------------------------------------------
-// LDS: four rows of nmax doubles per group -
+// LDS rows of NMAX = T K entries (the group capacity), in the order w, P, u, Q, V -
 //   w_l  d (diagonal) after assembly, then w = b/d after elimination;
-//   u_l  rhs after assembly, then u = rhs/d after elimination;
 //   P_l  the node's contribution a(w + 1) to its parent's diagonal, later the solution x = Delta v;
-//   Q_l  dv = v_parent - v after assembly (v itself at a root), then the contribution a(u - dv) to the parent's rhs.
+//   u_l  rhs after assembly, then u = rhs/d after elimination;
+//   Q_l  dv = v_parent - v after assembly (v itself at a root), then the contribution a(u - dv) to the parent's rhs;
+//   V_l  the membrane potential v, updated in place by the substitution.
+// While the compartments assemble, the rows w and P together hold each synapse's conductance sa g and the rows u
+// and Q its current sa g (v - e), for up to 2 NMAX synapses; the assembly keeps its results in registers until all
+// threads have read them.
+// and, for groups of up to 2048 nodes, the chunk's per-node constants: parent and children (32-bit), a, b, k.
 // With these, elimination of node i reads d_i, rhs_i and its children's contributions, and back-substitution is
-// x_i = u_i - w_i x_parent.
-// The membrane potential stays in global memory, double-buffered across steps: step k of a chunk reads v_{k-1}
-// from one buffer, adds the pending Delta v still held in P_l, and writes v_k to the other buffer, so a child reading
-// its parent's potential never races the parent's own update. The chunk's last Delta v is applied at its end.
-template <int T, typename S>
-__global__ void __launch_bounds__(T, 4) cn_interval(const KParams p) {
+// x_i = u_i - w_i x_parent. Each thread keeps the channel states of its compartments (node q = j T + t in register
+// slot j) in registers for the whole chunk; states and potentials cross global memory once per chunk.
+constexpr bool const_in_lds(int nmax) { return nmax <= 2048; }
+constexpr int lds_node_bytes(int nmax) { return const_in_lds(nmax) ? 72 : 40; }
+// waves per SIMD the register budget is sized for: more register slots per thread keep more compartments on chip
+constexpr int waves_for_slots(int K) { return K <= 1 ? 4 : (K == 2 ? 3 : (K == 4 ? 2 : 1)); }
+
+// UNI: every density-mechanism parameter is uniform (read from the LDS constants, not the per-node table)
+template <int T, int K, typename S, bool UNI>
+__global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const int NMAX = p.nmax;
-  double *w_l = reinterpret_cast<double *>(lds);
-  double *u_l = w_l + NMAX;
-  double *P_l = u_l + NMAX;
-  double *Q_l = P_l + NMAX;
+  constexpr int NMAX = T * K;
+  constexpr bool CL = const_in_lds(NMAX);
+  // fixed row offsets: they become immediate offsets of the LDS instructions
+  int *par_l = reinterpret_cast<int *>(lds);
+  uint32_t *ch_l = reinterpret_cast<uint32_t *>(par_l + NMAX);
+  double *w_l = reinterpret_cast<double *>(lds + (CL ? 8 * NMAX : 0));
+  double *P_l = w_l + NMAX;
+  double *u_l = P_l + NMAX;
+  double *Q_l = u_l + NMAX;
+  double *V_l = Q_l + NMAX;
+  double *GS_l = w_l;  // synapse conductances (2 NMAX entries)
+  double *IS_l = u_l;  // synapse currents (2 NMAX entries)
+  double *a_l = V_l + NMAX;
+  double *b_l = a_l + NMAX;
+  double *k_l = b_l + NMAX;
   uint64_t *ev = reinterpret_cast<uint64_t *>(lds + p.lds_ev_off);
   int *seg = reinterpret_cast<int *>(lds + p.lds_seg_off);
   int *lv = reinterpret_cast<int *>(lds + p.lds_lvl_off);
   uint8_t *bgm = reinterpret_cast<uint8_t *>(lds + p.lds_bg_off);
   int *misc = reinterpret_cast<int *>(lds + p.lds_misc_off);
   double *cst = reinterpret_cast<double *>(lds + p.lds_cst_off);
+  double *etab = reinterpret_cast<double *>(lds + p.lds_exp_off);
+  const lds_table *etab3 = (const lds_table *)etab;
 
   const int G = blockIdx.x;
   const int t = threadIdx.x;
@@ -233,6 +272,7 @@ __global__ void __launch_bounds__(T, 4) cn_interval(const KParams p) {
   // ---- prologue: level starts on chip, this interval's events sorted
   for (int L = t; L <= D; L += T) lv[L] = p.lvl_start[gd.lvl_base + L];
   if (t < N_PRM) cst[C_PRM + t] = p.prm_s[t];
+  if (t < 64) etab[t] = p.exp_tab[t];
   if (t == 0) {
     cst[C_Q10DT] = p.q10dt;
     cst[C_DT] = p.dt;
@@ -310,16 +350,55 @@ __global__ void __launch_bounds__(T, 4) cn_interval(const KParams p) {
     }
     seg[s] = a;
   }
-  __syncthreads();
 
+  auto c_a = [&](int q) { return CL ? a_l[q] : p.nrec[nb + q].a; };
+  auto c_b = [&](int q) { return CL ? b_l[q] : p.nrec[nb + q].b; };
+  auto c_k = [&](int q) { return CL ? k_l[q] : p.nrec[nb + q].k; };
+  auto c_par = [&](int q) { return CL ? par_l[q] : p.nidx[nb + q].par; };
+  auto c_ch = [&](int q) { return CL ? ch_l[q] : p.nidx[nb + q].ch; };
+  auto tri_in = [&](int q) { return TriIn{c_a(q), c_b(q), w_l[q], u_l[q], Q_l[q], c_ch(q)}; };
+  auto prm = [&](int col, int64_t i) -> double { return UNI ? cst[C_PRM + col] : p.prm[col * p.n_nodes_total + i]; };
   StRec<S> *st = static_cast<StRec<S> *>(p.st);
-  const int64_t sst = p.n_nodes_total;
   const SynRec<S> *syn = static_cast<const SynRec<S> *>(p.syn) + sb;
   S *sg = static_cast<S *>(p.syn_g) + sb;
-  double *const vbuf[2] = {p.v2 + nb, p.v + nb};  // step k writes vbuf[k & 1]; p.v holds v between chunks
-  const int lv1 = lv[1];
+  for (int q = t; q < N; q += T) {
+    V_l[q] = p.v[nb + q];
+    if (CL) {
+      const NodeRec nr = p.nrec[nb + q];
+      const NodeIdx nx = p.nidx[nb + q];
+      a_l[q] = nr.a;
+      b_l[q] = nr.b;
+      k_l[q] = nr.k;
+      par_l[q] = nx.par;
+      ch_l[q] = nx.ch;
+    }
+  }
+  // per-slot registers for the whole chunk: channel states, parent, counts-and-flags, first synapse
+  StRec<S> rs[K];
+  int rpar[K], rsyn0[K];
+  uint32_t rpk[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int q = j * T + t;
+    rs[j] = StRec<S>{};
+    rpar[j] = -1;
+    rpk[j] = 0u;
+    rsyn0[j] = 0;
+    if (q < N) {
+      const NodeIdx nx = p.nidx[nb + q];
+      rpar[j] = nx.par;
+      rpk[j] = nx.pk;
+      rsyn0[j] = nx.syn0;
+      rs[j] = st[nb + q];
+    }
+  }
   if (!p.has_bg)
     for (int i = t; i < n_syn; i += T) bgm[i] = 0;
+  const int lv1 = lv[1];
+  const double theta0 = t < lv1 ? p.cell_theta[gd.cell_base + t] : 0.0;
+  // synapse terms are staged on chip when the group's synapses fit the rows
+  const bool staged = n_syn <= 2 * NMAX;
+  __syncthreads();
 
   for (int64_t n = n_begin; n < n_end; ++n) {
     const int s = (int)(n - ival * M);
@@ -344,149 +423,147 @@ __global__ void __launch_bounds__(T, 4) cn_interval(const KParams p) {
       }
     }
     __syncthreads();
+    const uint32_t bsh = (uint32_t)(n & 3);
+    // ---- S: synapses, one thread per synapse over contiguous records: conductance gs = sa g (with this step's
+    // background event) and current gs (v - e) to LDS; the step's decay is applied to g ahead of the next delivery
+    if (staged) {
+      for (int ls = t; ls < n_syn; ls += T) {
+        const SynRec<S> sy = syn[ls];
+        S g = sg[ls];
+        if ((bgm[ls] >> bsh) & 1u) g += sy.wbg;
+        const double gs = sy.sa * (double)g;
+        GS_l[ls] = gs;
+        IS_l[ls] = gs * (V_l[sy.q] - sy.e);
+        sg[ls] = g * sy.f;
+      }
+      __syncthreads();
+    }
     // ---- C: states, currents, conductances and the compartment's own axial terms
     const bool pend = n > 0;
-    const uint32_t bsh = (uint32_t)(n & 3);
-    const int kk = (int)(n - n_begin);
-    const bool first = kk == 0;
-    const double *vr = first ? p.v + nb : vbuf[(kk - 1) & 1];  // v_{k-1} (pending Delta v in P_l unless first)
-    double *vw = vbuf[kk & 1];
     const S q10dt = (S)cst[C_Q10DT];
     const S sdt = (S)cst[C_DT];
     const S ca_fm = (S)cst[C_CA_FM], ca_fr = (S)cst[C_CA_FR], ca_k = (S)cst[C_CA_K];
-    // records and states of the thread's next compartment are loaded while the current one is computed
-    NodeRec nr_n{};
-    NodeIdx nx_n{};
-    StRec<S> sr_n{};
-    double v_n = 0.0;
-    if (t < N) {
-      nr_n = p.nrec[nb + t];
-      nx_n = p.nidx[nb + t];
-      sr_n = st[nb + t];
-      v_n = vr[t];
-    }
-#pragma unroll 1
-    for (int q = t; q < N; q += T) {
-      const int64_t i = nb + q;
-      const NodeRec nr = nr_n;
-      const NodeIdx nx = nx_n;
-      StRec<S> sr = sr_n;
-      const double vpar_old = nx.par >= 0 ? vr[nx.par] : 0.0;
-      const double v = first ? v_n : v_n + P_l[q];
-      if (q + T < N) {
-        nr_n = p.nrec[i + T];
-        nx_n = p.nidx[i + T];
-        sr_n = st[i + T];
-        v_n = vr[q + T];
-      }
-      vw[q] = v;
-      double rhs = 0.0, d = 0.0;
-      const uint32_t mf = nx.pk >> 24;
-      const bool has_st = (mf & (MF_HH | MF_KM | MF_CAHI)) != 0;
-      if (pend && has_st) {
-        if (mf & MF_HH) hh_advance<S>(v, q10dt, sr.m, sr.h, sr.n);
-        if (mf & MF_KM) km_advance<S>(v, sdt, sr.kn);
-        if (mf & MF_CAHI) {
-          const S gca = (S)(p.prm ? p.prm[P_CA_G * sst + i] : cst[C_PRM + P_CA_G]);
-          cahi_advance<S>(v, ca_fm, ca_fr, ca_k, gca, sr.cm, sr.cai);
+    double od[K], orhs[K], odv[K];  // assembly results, written once every thread has read the staged synapses
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int q = j * T + t;
+      od[j] = orhs[j] = odv[j] = 0.0;
+      if (q < N) {
+        const int64_t i = nb + q;
+        const int par = rpar[j];
+        const uint32_t pk = rpk[j];
+        const double v = V_l[q];
+        double rhs = 0.0, d = 0.0;
+        const uint32_t mf = pk >> 24;
+        StRec<S> &sr = rs[j];
+        if (pend) {
+          if (mf & MF_HH) hh_advance<S>(v, q10dt, sr.m, sr.h, sr.n, etab3);
+          if (mf & MF_KM) km_advance<S>(v, sdt, sr.kn, etab3);
+          if (mf & MF_CAHI) cahi_advance<S>(v, ca_fm, ca_fr, ca_k, (S)prm(P_CA_G, i), sr.cm, sr.cai, etab3);
         }
-        st[i] = sr;
+        if (mf & MF_HH) {
+          const double gnab = prm(P_HH_GNA, i), gkb = prm(P_HH_GK, i), gl = prm(P_HH_GL, i), el = prm(P_HH_EL, i);
+          const double gna = (double)((S)gnab * (sr.m * sr.m * sr.m * sr.h));
+          const double gk = (double)((S)gkb * ((sr.n * sr.n) * (sr.n * sr.n)));
+          rhs -= gna * (v - 50.0) + gk * (v + 77.0) + gl * (v - el);
+          d += gna + gk + gl;
+        }
+        if (mf & MF_PAS) {
+          const double g = prm(P_PAS_G, i), e = prm(P_PAS_E, i);
+          rhs -= g * (v - e);
+          d += g;
+        }
+        if (mf & MF_KM) {
+          const double g = (double)((S)prm(P_KM_G, i) * sr.kn);
+          rhs -= g * (v + 77.0);
+          d += g;
+        }
+        if (mf & MF_CAHI) {
+          const double g = (double)((S)prm(P_CA_G, i) * (sr.cm * sr.cm));
+          rhs -= g * (v - 120.0);
+          d += g;
+        }
+        const int n_icl = (int)((pk >> 16) & 0xFFu);
+        if (n_icl) {
+          const IclRec *ic = p.icl + gd.icl_base + p.nd_icl0[i];
+          for (int c = 0; c < n_icl; ++c)
+            if (ic[c].on <= n && n < ic[c].off) rhs += ic[c].cur;
+        }
+        const int n_s = (int)(pk & 0xFFFFu);
+        if (n_s) {
+          const int syn0 = rsyn0[j];
+          if (staged) {
+            for (int c = syn0; c < syn0 + n_s; ++c) {
+              rhs -= IS_l[c];
+              d += GS_l[c];
+            }
+          } else {  // groups with more synapses than a row holds: the same terms, computed here
+            for (int ls = syn0; ls < syn0 + n_s; ++ls) {
+              const SynRec<S> sy = syn[ls];
+              S g = sg[ls];
+              if ((bgm[ls] >> bsh) & 1u) g += sy.wbg;
+              const double gs = sy.sa * (double)g;
+              rhs -= gs * (v - sy.e);
+              d += gs;
+              sg[ls] = g * sy.f;
+            }
+          }
+        }
+        d += c_k(q);
+        double dvq = v;  // a root keeps its own potential for threshold detection
+        if (par >= 0) {
+          dvq = V_l[par] - v;
+          rhs -= c_b(q) * dvq;
+        }
+        od[j] = d;
+        orhs[j] = rhs;
+        odv[j] = dvq;
       }
-      if (mf & MF_HH) {
-        const double gnab = p.prm ? p.prm[P_HH_GNA * sst + i] : cst[C_PRM + P_HH_GNA];
-        const double gkb = p.prm ? p.prm[P_HH_GK * sst + i] : cst[C_PRM + P_HH_GK];
-        const double gl = p.prm ? p.prm[P_HH_GL * sst + i] : cst[C_PRM + P_HH_GL];
-        const double el = p.prm ? p.prm[P_HH_EL * sst + i] : cst[C_PRM + P_HH_EL];
-        const double gna = (double)((S)gnab * (sr.m * sr.m * sr.m * sr.h));
-        const double gk = (double)((S)gkb * ((sr.n * sr.n) * (sr.n * sr.n)));
-        rhs -= gna * (v - 50.0) + gk * (v + 77.0) + gl * (v - el);
-        d += gna + gk + gl;
-      }
-      if (mf & MF_PAS) {
-        const double g = p.prm ? p.prm[P_PAS_G * sst + i] : cst[C_PRM + P_PAS_G];
-        const double e = p.prm ? p.prm[P_PAS_E * sst + i] : cst[C_PRM + P_PAS_E];
-        rhs -= g * (v - e);
-        d += g;
-      }
-      if (mf & MF_KM) {
-        const double g = (double)((S)(p.prm ? p.prm[P_KM_G * sst + i] : cst[C_PRM + P_KM_G]) * sr.kn);
-        rhs -= g * (v + 77.0);
-        d += g;
-      }
-      if (mf & MF_CAHI) {
-        const S gca = (S)(p.prm ? p.prm[P_CA_G * sst + i] : cst[C_PRM + P_CA_G]);
-        const double g = (double)(gca * (sr.cm * sr.cm));
-        rhs -= g * (v - 120.0);
-        d += g;
-      }
-      const int n_icl = (int)((nx.pk >> 16) & 0xFFu);
-      if (n_icl) {
-        const IclRec *ic = p.icl + gd.icl_base + p.nd_icl0[i];
-        for (int c = 0; c < n_icl; ++c)
-          if (ic[c].on <= n && n < ic[c].off) rhs += ic[c].cur;
-      }
-      const int n_s = (int)(nx.pk & 0xFFFFu);
-      for (int c = 0; c < n_s; ++c) {
-        const int ls = nx.syn0 + c;
-        const SynRec<S> sr = syn[ls];
-        S g = sg[ls];
-        if ((bgm[ls] >> bsh) & 1u) g += sr.wbg;
-        const double gs = nr.sa * (double)g;
-        rhs -= gs * (v - sr.e);
-        d += gs;
-        sg[ls] = g * sr.f;  // decay of this step, applied ahead of the next delivery
-      }
-      d += nr.k;
-      double dvq = v;  // a root keeps its own potential here for threshold detection
-      if (nx.par >= 0) {
-        const double vpar = first ? vpar_old : vpar_old + P_l[nx.par];
-        const double dv = vpar - v;
-        rhs -= nr.b * dv;
-        dvq = dv;
-      }
-      w_l[q] = d;
-      u_l[q] = rhs;
-      Q_l[q] = dvq;
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
-    // ---- T: elimination, deepest level first, one thread per node of the level. Each thread's node records for
-    // the next three levels are in flight while the current level is processed (they are loop invariant, but
-    // too many to keep on chip for the whole chunk).
-    const uint32_t root_ch = t < lv1 ? p.nidx[nb + t].ch : 0u;  // roots' children, used after the elimination
-    {
-      SolveNode c0n, c1n, c2n;
-      int Lc = D - 1;
-      c0n = solve_node(p, nb, lv, Lc, t);
-      c1n = solve_node(p, nb, lv, Lc - 1, t);
-      c2n = solve_node(p, nb, lv, Lc - 2, t);
-      for (; Lc >= 1; --Lc) {
-        const SolveNode cur = c0n;
-        c0n = c1n;
-        c1n = c2n;
-        c2n = solve_node(p, nb, lv, Lc - 3, t);
-        const int q = lv[Lc] + t, hi = lv[Lc + 1];
-        if (q < hi) tri_node(q, cur.a, cur.b, cur.ch, w_l, u_l, P_l, Q_l);
-        for (int q2 = q + T; q2 < hi; q2 += T) {  // levels wider than the group's threads
-          const NodeRec r2 = p.nrec[nb + q2];
-          tri_node(q2, r2.a, r2.b, p.nidx[nb + q2].ch, w_l, u_l, P_l, Q_l);
-        }
-        __syncthreads();
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int q = j * T + t;
+      if (q < N) {
+        w_l[q] = od[j];
+        u_l[q] = orhs[j];
+        Q_l[q] = odv[j];
       }
     }
+    __syncthreads();
+    // ---- T: elimination, deepest level first, one thread per node of the level. A level's own inputs are final
+    // before it starts, so each thread loads them one level ahead; after a barrier only the children's
+    // contributions remain to be read. Level bounds are read two levels ahead.
+    int hi = lv[D], lo = lv[D - 1], lo_n = D >= 2 ? lv[D - 2] : 0;
+    int q = lo + t;
+    TriIn cur{};
+    if (q < hi) cur = tri_in(q);
+    for (int L = D - 1; L >= 1; --L) {  // level L is [lo, hi), level L - 1 is [lo_n, lo)
+      const int lo_nn = L >= 2 ? lv[L - 2] : 0;
+      const int nq = lo_n + t;
+      TriIn nxt{};
+      if (nq < lo) nxt = tri_in(nq);
+      if (q < hi) tri_node(q, cur, w_l, u_l, P_l, Q_l);
+      for (int q2 = q + T; q2 < hi; q2 += T) tri_node(q2, tri_in(q2), w_l, u_l, P_l, Q_l);  // wide levels
+      __syncthreads();
+      hi = lo;
+      lo = lo_n;
+      lo_n = lo_nn;
+      q = nq;
+      cur = nxt;
+    }
     // ---- R: roots (level 0 holds the group's cells in order): solve, v update, threshold detection
-    for (int q = t; q < lv1; q += T) {
-      const uint32_t ch = q == t ? root_ch : p.nidx[nb + q].ch;
-      double d = w_l[q], rhs = u_l[q];
-      const int c0 = (int)(ch & 0xFFFFu), cn = (int)(ch >> 16);
-      for (int c = c0; c < c0 + cn; ++c) {
-        d -= P_l[c];
-        rhs -= Q_l[c];
-      }
-      const double x = rhs / d;
-      const double vold = Q_l[q];
-      const double vnew = vold + x;
-      P_l[q] = x;
-      const double th = p.cell_theta[gd.cell_base + q];
+    for (; q < hi; q += T) {
+      const TriIn x = q == t ? cur : tri_in(q);
+      double d = x.d, rhs = x.r;
+      gather_children(x.ch, P_l, Q_l, d, rhs);
+      const double xs = rhs / d;
+      const double vold = x.dv;
+      const double vnew = vold + xs;
+      P_l[q] = xs;
+      V_l[q] = vnew;
+      const double th = q == t ? theta0 : p.cell_theta[gd.cell_base + q];
       if (vold < th && th <= vnew) {
         const int idx = atomicAdd(&misc[1], 1);
         p.gsp_pack[gd.spk_base + idx] = q | ((s + 1) << 16);
@@ -495,33 +572,59 @@ __global__ void __launch_bounds__(T, 4) cn_interval(const KParams p) {
       if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
     }
     __syncthreads();
-    // ---- B: substitution, root to leaves: x = u - w x_parent (parents of the next three levels in flight)
+    // ---- B: substitution, root to leaves: x = u - w x_parent, v += x. A level's u, w, parent and v are final
+    // after the elimination, so each thread loads them one level ahead; after a barrier only x_parent remains.
     {
-      int p0 = par_of(p, nb, lv, D, 1, t), p1 = par_of(p, nb, lv, D, 2, t), p2 = par_of(p, nb, lv, D, 3, t);
-      for (int L = 1; L < D; ++L) {
-        const int lo = lv[L], hi = lv[L + 1];
-        const int q = lo + t, par = p0;
-        p0 = p1;
-        p1 = p2;
-        p2 = par_of(p, nb, lv, D, L + 3, t);
-        if (q < hi) {
-          const double x = u_l[q] - w_l[q] * P_l[par];
-          P_l[q] = x;
+      int bhi = D > 1 ? lv[2] : 0, bhi_n = D > 2 ? lv[3] : 0;
+      int bq = (D > 1 ? lv[1] : 0) + t;
+      double cu = 0.0, cw = 0.0, cv = 0.0;
+      int cp = 0;
+      if (bq < bhi) {
+        cu = u_l[bq];
+        cw = w_l[bq];
+        cv = V_l[bq];
+        cp = c_par(bq);
+      }
+      for (int L = 1; L < D; ++L) {  // level L is [bq - t, bhi), level L + 1 is [bhi, bhi_n)
+        const int bhi_nn = L + 3 <= D ? lv[L + 3] : 0;
+        const int nq = bhi + t;
+        double nu = 0.0, nw = 0.0, nv = 0.0;
+        int np = 0;
+        if (L + 1 < D && nq < bhi_n) {
+          nu = u_l[nq];
+          nw = w_l[nq];
+          nv = V_l[nq];
+          np = c_par(nq);
         }
-        for (int q2 = q + T; q2 < hi; q2 += T) {
-          const double x = u_l[q2] - w_l[q2] * P_l[p.nidx[nb + q2].par];
+        if (bq < bhi) {
+          const double x = cu - cw * P_l[cp];
+          P_l[bq] = x;
+          V_l[bq] = cv + x;
+        }
+        for (int q2 = bq + T; q2 < bhi; q2 += T) {  // wide levels
+          const double x = u_l[q2] - w_l[q2] * P_l[c_par(q2)];
           P_l[q2] = x;
+          V_l[q2] += x;
         }
         __syncthreads();
+        bq = nq;
+        bhi = bhi_n;
+        bhi_n = bhi_nn;
+        cu = nu;
+        cw = nw;
+        cv = nv;
+        cp = np;
       }
     }
   }
 
-  // ---- epilogue: apply the last step's Delta v; the chunk's spikes (count in gsp_cnt) are recorded and fanned
-  // out by cn_fanout
-  {
-    const double *vl = vbuf[(int)(n_end - 1 - n_begin) & 1];
-    for (int q = t; q < N; q += T) p.v[nb + q] = vl[q] + P_l[q];
+  // ---- epilogue: potentials and states back to global memory; the chunk's spikes (count in gsp_cnt) are recorded
+  // and fanned out by cn_fanout
+  for (int q = t; q < N; q += T) p.v[nb + q] = V_l[q];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int q = j * T + t;
+    if (q < N) st[nb + q] = rs[j];
   }
   if (t == 0) {
     p.gsp_cnt[G] = misc[1];
@@ -602,6 +705,10 @@ __global__ void cn_fill_i32(int32_t *p, int64_t n, int32_t v) {
 // is applied at the start of the next), so apply it to a copy here.
 template <typename S>
 __global__ void cn_read_state(const KParams p, int64_t n_nodes, int64_t step, int type, int which, double *out) {
+  __shared__ double tab[64];
+  if (threadIdx.x < 64) tab[threadIdx.x] = p.exp_tab[threadIdx.x];
+  __syncthreads();
+  const lds_table *et = (const lds_table *)tab;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n_nodes) return;
   const double v = p.v[i];
@@ -609,14 +716,14 @@ __global__ void cn_read_state(const KParams p, int64_t n_nodes, int64_t step, in
   StRec<S> sr = static_cast<const StRec<S> *>(p.st)[i];
   const int64_t sst = p.n_nodes_total;
   if (type == 0) {
-    if (pend) hh_advance<S>(v, (S)p.q10dt, sr.m, sr.h, sr.n);
+    if (pend) hh_advance<S>(v, (S)p.q10dt, sr.m, sr.h, sr.n, et);
     out[i] = which == 0 ? (double)sr.m : (which == 1 ? (double)sr.h : (double)sr.n);
   } else if (type == 2) {
-    if (pend) km_advance<S>(v, (S)p.dt, sr.kn);
+    if (pend) km_advance<S>(v, (S)p.dt, sr.kn, et);
     out[i] = (double)sr.kn;
   } else if (type == 3) {
     const S gca = (S)(p.prm ? p.prm[P_CA_G * sst + i] : p.prm_s[P_CA_G]);
-    if (pend) cahi_advance<S>(v, (S)p.ca_fm, (S)p.ca_fr, (S)p.ca_k, gca, sr.cm, sr.cai);
+    if (pend) cahi_advance<S>(v, (S)p.ca_fm, (S)p.ca_fr, (S)p.ca_k, gca, sr.cm, sr.cai, et);
     out[i] = which == 0 ? (double)sr.cm : (double)sr.cai;
   }
 }
@@ -625,24 +732,49 @@ __global__ void cn_read_state(const KParams p, int64_t n_nodes, int64_t step, in
 // launch wrappers (host side)
 using IntervalFn = void (*)(const KParams);
 
-static IntervalFn interval_fn(bool fp32, int threads) {
-  if (threads == 256) return fp32 ? cn_interval<256, float> : cn_interval<256, double>;
-  if (threads == 512) return fp32 ? cn_interval<512, float> : cn_interval<512, double>;
-  if (threads == 128) return fp32 ? cn_interval<128, float> : cn_interval<128, double>;
+template <typename S, bool UNI>
+static IntervalFn interval_fn_s(int threads, int slots) {
+  if (threads == 256) {
+    switch (slots) {
+      case 1: return cn_interval<256, 1, S, UNI>;
+      case 2: return cn_interval<256, 2, S, UNI>;
+      case 4: return cn_interval<256, 4, S, UNI>;
+      default: break;
+    }
+  } else if (threads == 512) {
+    switch (slots) {
+      case 2: return cn_interval<512, 2, S, UNI>;
+      case 4: return cn_interval<512, 4, S, UNI>;
+      case 8: return cn_interval<512, 8, S, UNI>;
+      default: break;
+    }
+  } else if (threads == 128) {
+    switch (slots) {
+      case 2: return cn_interval<128, 2, S, UNI>;
+      case 4: return cn_interval<128, 4, S, UNI>;
+      case 8: return cn_interval<128, 8, S, UNI>;
+      default: break;
+    }
+  }
   return nullptr;
 }
 
-hipError_t set_interval_lds(bool fp32, int threads, int slots, int lds_bytes) {
-  (void)slots;
-  IntervalFn fn = interval_fn(fp32, threads);
+static IntervalFn interval_fn(bool fp32, int threads, int slots, bool uni) {
+  if (uni) return fp32 ? interval_fn_s<float, true>(threads, slots) : interval_fn_s<double, true>(threads, slots);
+  return fp32 ? interval_fn_s<float, false>(threads, slots) : interval_fn_s<double, false>(threads, slots);
+}
+
+int interval_node_bytes(int nmax) { return lds_node_bytes(nmax); }
+
+hipError_t set_interval_lds(bool fp32, int threads, int slots, bool uni, int lds_bytes) {
+  IntervalFn fn = interval_fn(fp32, threads, slots, uni);
   if (!fn) return hipErrorInvalidValue;
   return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                              lds_bytes);
 }
 
 hipError_t launch_interval(const KParams &p, bool fp32, int threads, int slots, int lds_bytes, hipStream_t st) {
-  (void)slots;
-  IntervalFn fn = interval_fn(fp32, threads);
+  IntervalFn fn = interval_fn(fp32, threads, slots, p.prm == nullptr);
   if (!fn) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(p.n_groups), dim3(threads), lds_bytes, st, p);
   return hipGetLastError();
