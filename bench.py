@@ -159,7 +159,8 @@ def main():
                    "n_cells": m.n_cells, "n_comp": m.n_comp, "n_syn": m.n_syn, "interval_steps": r64["M"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "cn_interval<256,4,double>", "kernel_ms": r64["kernel_ms"],
+                     "kernel": "cn_interval<%d,%d,double>" % (r64["info"]["group_threads"], r64["info"]["group_slots"]),
+                     "kernel_ms": r64["kernel_ms"],
                      "algorithmic_bytes_per_launch": per_launch},
     }
     if r32 is not None:

@@ -23,7 +23,7 @@
 namespace cn {
 hipError_t launch_interval(const KParams &p, bool fp32, int threads, int slots, int lds_bytes, hipStream_t st);
 hipError_t set_interval_lds(bool fp32, int threads, int slots, bool uni, int lds_bytes);
-int interval_node_bytes(int nmax);
+int interval_row_bytes(int nmax);
 hipError_t launch_advance(int64_t *ctl, int32_t M, hipStream_t st);
 hipError_t launch_fanout(const KParams &p, hipStream_t st);
 hipError_t launch_set_ctl(int64_t *ctl, int64_t n_begin, int64_t n_target, hipStream_t st);
@@ -317,15 +317,19 @@ void build_layout(cn_model *m) {
 
   // group shape: T threads x K register slots per thread, capacity T*K compartments. Shapes compiled:
   // T = 128 with K = 2, 4, 8; T = 256 with K = 1, 2, 4; T = 512 with K = 2, 4, 8.
+  // Large models take groups of 1024 or more compartments on 512 threads: two slots per thread keep the register
+  // budget at four waves per SIMD, which hides the latency of the level sweeps; small models take smaller groups
+  // so that there are enough of them to fill the device.
+  const bool large = N >= (int64_t)1024 * 1024;
   int T = m->opt.group_threads;
-  if (T == 0) T = max_cell <= 1024 ? 256 : 512;
+  if (T == 0) T = (large || max_cell > 1024) ? 512 : 256;
   if (T != 128 && T != 256 && T != 512) throw Err{CN_E_INVALID, "group_threads must be 128, 256 or 512"};
   const int kmin = T == 256 ? 1 : 2, kmax = T == 256 ? 4 : 8;
   int K = kmin;
   while (K < kmax && T * K < max_cell) K *= 2;
   if (T * K < max_cell) throw Err{CN_E_INVALID, "a cell has more compartments (" + std::to_string(max_cell) +
                                                    ") than one cell group holds (" + std::to_string(T * K) + ")"};
-  if (K < 4 && N >= (int64_t)T * 4 * 512) K = 4;  // large models: fuller groups
+  if (T == 256 && K < 4 && large) K = 4;  // large models on 256 threads: fuller groups
   m->threads = T;
   m->slots = K;
   m->nmax = T * K;
@@ -873,7 +877,7 @@ static void prepare_dt(cn_model *m, double dt) {
   // constants (three doubles and three 32-bit indices) for groups of up to 2048 nodes, event keys, step segments,
   // level starts, background bits, counters
   p.nmax = m->nmax;
-  int off = interval_node_bytes(m->nmax) * m->nmax;
+  int off = interval_row_bytes(m->nmax);
   p.lds_ev_off = off;
   off += p.ev_cap * 8;
   p.lds_seg_off = off;

@@ -169,35 +169,34 @@ struct TriIn {
 };
 
 // subtract the children's contributions (children c0 .. c0 + count - 1 on the level below) from d and rhs, in child
-// order; the loads are issued four children at a time so that one LDS round trip serves most nodes
-__device__ __forceinline__ void gather_children(uint32_t ch, const double *P_l, const double *Q_l, double &d,
-                                                double &rhs) {
-  const int c0 = (int)(ch & 0xFFFFu), ce = c0 + (int)(ch >> 16);
-  for (int c = c0; c < ce; c += 4) {
-    const int c1 = min(c + 1, ce - 1), c2 = min(c + 2, ce - 1), c3 = min(c + 3, ce - 1);
-    const double p0 = P_l[c], p1 = P_l[c1], p2 = P_l[c2], p3 = P_l[c3];
-    const double q0 = Q_l[c], q1 = Q_l[c1], q2 = Q_l[c2], q3 = Q_l[c3];
-    d -= p0;
-    rhs -= q0;
-    if (c + 1 < ce) {
-      d -= p1;
-      rhs -= q1;
-    }
-    if (c + 2 < ce) {
-      d -= p2;
-      rhs -= q2;
-    }
-    if (c + 3 < ce) {
-      d -= p3;
-      rhs -= q3;
-    }
+// order. The first four are read unconditionally, an absent child from the zero entry `zero` of the rows (x - 0
+// is x exactly), so one LDS round trip serves most nodes without per-child masking.
+__device__ __forceinline__ void gather_children(uint32_t ch, int zero, const double *P_l, const double *Q_l,
+                                                double &d, double &rhs) {
+  const int c0 = (int)(ch & 0xFFFFu), cn = (int)(ch >> 16);
+  const int i0 = cn > 0 ? c0 : zero, i1 = cn > 1 ? c0 + 1 : zero, i2 = cn > 2 ? c0 + 2 : zero,
+            i3 = cn > 3 ? c0 + 3 : zero;
+  const double p0 = P_l[i0], p1 = P_l[i1], p2 = P_l[i2], p3 = P_l[i3];
+  const double q0 = Q_l[i0], q1 = Q_l[i1], q2 = Q_l[i2], q3 = Q_l[i3];
+  d -= p0;
+  rhs -= q0;
+  d -= p1;
+  rhs -= q1;
+  d -= p2;
+  rhs -= q2;
+  d -= p3;
+  rhs -= q3;
+  for (int c = c0 + 4; c < c0 + cn; ++c) {
+    d -= P_l[c];
+    rhs -= Q_l[c];
   }
 }
 
 // one node of the elimination: gather the children's contributions, then publish this node's own
-__device__ __forceinline__ void tri_node(int q, const TriIn &x, double *w_l, double *u_l, double *P_l, double *Q_l) {
+__device__ __forceinline__ void tri_node(int q, const TriIn &x, int zero, double *w_l, double *u_l, double *P_l,
+                                         double *Q_l) {
   double d = x.d, rhs = x.r;
-  gather_children(x.ch, P_l, Q_l, d, rhs);
+  gather_children(x.ch, zero, P_l, Q_l, d, rhs);
   const double ri = rcp64(d);
   const double w = ri * x.b, u = ri * rhs;
   w_l[q] = w;
@@ -207,21 +206,23 @@ __device__ __forceinline__ void tri_node(int q, const TriIn &x, double *w_l, dou
 }
 
 // ------------------------------------------------------------------------------------------------------------------
-// LDS rows of NMAX = T K entries (the group capacity), in the order w, P, u, Q, V -
+// LDS rows of NMAX = T K entries (the group capacity) and one more, in the order w, P, u, Q, V -
 //   w_l  d (diagonal) after assembly, then w = b/d after elimination;
 //   P_l  the node's contribution a(w + 1) to its parent's diagonal, later the solution x = Delta v;
 //   u_l  rhs after assembly, then u = rhs/d after elimination;
 //   Q_l  dv = v_parent - v after assembly (v itself at a root), then the contribution a(u - dv) to the parent's rhs;
 //   V_l  the membrane potential v, updated in place by the substitution.
-// While the compartments assemble, the rows w and P together hold each synapse's conductance sa g and the rows u
-// and Q its current sa g (v - e), for up to 2 NMAX synapses; the assembly keeps its results in registers until all
-// threads have read them.
-// and, for groups of up to 2048 nodes, the chunk's per-node constants: parent and children (32-bit), a, b, k.
+// Entry NMAX of the P and Q rows is zero: the children gather reads it for absent children. While the compartments
+// assemble, the rows w and P together hold each synapse's conductance sa g and the rows u and Q its current
+// sa g (v - e), for up to 2 NMAX synapses (short of the zero entries); the assembly keeps its results in registers
+// until all threads have read them. For groups of up to 2048 nodes, further rows hold the chunk's per-node
+// constants: parent and children (32-bit), a, b, k.
 // With these, elimination of node i reads d_i, rhs_i and its children's contributions, and back-substitution is
 // x_i = u_i - w_i x_parent. Each thread keeps the channel states of its compartments (node q = j T + t in register
 // slot j) in registers for the whole chunk; states and potentials cross global memory once per chunk.
 constexpr bool const_in_lds(int nmax) { return nmax <= 2048; }
-constexpr int lds_node_bytes(int nmax) { return const_in_lds(nmax) ? 72 : 40; }
+// bytes of the node rows: two 32-bit rows of nmax and eight double rows of nmax + 1 entries, or five double rows
+constexpr int lds_row_bytes(int nmax) { return const_in_lds(nmax) ? 8 * nmax + 64 * (nmax + 1) : 40 * (nmax + 1); }
 // waves per SIMD the register budget is sized for: more register slots per thread keep more compartments on chip
 constexpr int waves_for_slots(int K) { return K <= 1 ? 4 : (K == 2 ? 3 : (K == 4 ? 2 : 1)); }
 
@@ -234,16 +235,17 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
   // fixed row offsets: they become immediate offsets of the LDS instructions
   int *par_l = reinterpret_cast<int *>(lds);
   uint32_t *ch_l = reinterpret_cast<uint32_t *>(par_l + NMAX);
+  constexpr int RS = NMAX + 1;  // double row stride; entry NMAX of P and Q is the zero entry
   double *w_l = reinterpret_cast<double *>(lds + (CL ? 8 * NMAX : 0));
-  double *P_l = w_l + NMAX;
-  double *u_l = P_l + NMAX;
-  double *Q_l = u_l + NMAX;
-  double *V_l = Q_l + NMAX;
+  double *P_l = w_l + RS;
+  double *u_l = P_l + RS;
+  double *Q_l = u_l + RS;
+  double *V_l = Q_l + RS;
   double *GS_l = w_l;  // synapse conductances (2 NMAX entries)
   double *IS_l = u_l;  // synapse currents (2 NMAX entries)
-  double *a_l = V_l + NMAX;
-  double *b_l = a_l + NMAX;
-  double *k_l = b_l + NMAX;
+  double *a_l = V_l + RS;
+  double *b_l = a_l + RS;
+  double *k_l = b_l + RS;
   uint64_t *ev = reinterpret_cast<uint64_t *>(lds + p.lds_ev_off);
   int *seg = reinterpret_cast<int *>(lds + p.lds_seg_off);
   int *lv = reinterpret_cast<int *>(lds + p.lds_lvl_off);
@@ -396,9 +398,18 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     for (int i = t; i < n_syn; i += T) bgm[i] = 0;
   const int lv1 = lv[1];
   const double theta0 = t < lv1 ? p.cell_theta[gd.cell_base + t] : 0.0;
+  if (t == 0) {
+    P_l[NMAX] = 0.0;
+    Q_l[NMAX] = 0.0;
+  }
+  // level starts, lane L of every wave holding lv[L]: read back with a lane read instead of an LDS round trip
+  const int lvr = (t & 63) <= D ? lv[t & 63] : 0;
+  auto LVB = [&](int L) -> int { return D < 64 ? __builtin_amdgcn_readlane(lvr, L) : lv[L]; };
   // synapse terms are staged on chip when the group's synapses fit the rows
   const bool staged = n_syn <= 2 * NMAX;
   __syncthreads();
+  // everything but the compartments' assembly is latency-bound and runs at the higher wave priority
+  __builtin_amdgcn_s_setprio(2);
 
   for (int64_t n = n_begin; n < n_end; ++n) {
     const int s = (int)(n - ival * M);
@@ -438,7 +449,9 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
       }
       __syncthreads();
     }
-    // ---- C: states, currents, conductances and the compartment's own axial terms
+    // ---- C: states, currents, conductances and the compartment's own axial terms. Throughput work: it runs at
+    // the lower wave priority, so that a co-resident group's latency-bound sweeps issue ahead of it.
+    __builtin_amdgcn_s_setprio(0);
     const bool pend = n > 0;
     const S q10dt = (S)cst[C_Q10DT];
     const S sdt = (S)cst[C_DT];
@@ -532,20 +545,21 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
       }
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(2);
     // ---- T: elimination, deepest level first, one thread per node of the level. A level's own inputs are final
     // before it starts, so each thread loads them one level ahead; after a barrier only the children's
     // contributions remain to be read. Level bounds are read two levels ahead.
-    int hi = lv[D], lo = lv[D - 1], lo_n = D >= 2 ? lv[D - 2] : 0;
+    int hi = LVB(D), lo = LVB(D - 1), lo_n = D >= 2 ? LVB(D - 2) : 0;
     int q = lo + t;
     TriIn cur{};
     if (q < hi) cur = tri_in(q);
     for (int L = D - 1; L >= 1; --L) {  // level L is [lo, hi), level L - 1 is [lo_n, lo)
-      const int lo_nn = L >= 2 ? lv[L - 2] : 0;
+      const int lo_nn = L >= 2 ? LVB(L - 2) : 0;
       const int nq = lo_n + t;
       TriIn nxt{};
       if (nq < lo) nxt = tri_in(nq);
-      if (q < hi) tri_node(q, cur, w_l, u_l, P_l, Q_l);
-      for (int q2 = q + T; q2 < hi; q2 += T) tri_node(q2, tri_in(q2), w_l, u_l, P_l, Q_l);  // wide levels
+      if (q < hi) tri_node(q, cur, NMAX, w_l, u_l, P_l, Q_l);
+      for (int q2 = q + T; q2 < hi; q2 += T) tri_node(q2, tri_in(q2), NMAX, w_l, u_l, P_l, Q_l);  // wide levels
       __syncthreads();
       hi = lo;
       lo = lo_n;
@@ -557,7 +571,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     for (; q < hi; q += T) {
       const TriIn x = q == t ? cur : tri_in(q);
       double d = x.d, rhs = x.r;
-      gather_children(x.ch, P_l, Q_l, d, rhs);
+      gather_children(x.ch, NMAX, P_l, Q_l, d, rhs);
       const double xs = rhs / d;
       const double vold = x.dv;
       const double vnew = vold + xs;
@@ -575,8 +589,8 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     // ---- B: substitution, root to leaves: x = u - w x_parent, v += x. A level's u, w, parent and v are final
     // after the elimination, so each thread loads them one level ahead; after a barrier only x_parent remains.
     {
-      int bhi = D > 1 ? lv[2] : 0, bhi_n = D > 2 ? lv[3] : 0;
-      int bq = (D > 1 ? lv[1] : 0) + t;
+      int bhi = D > 1 ? LVB(2) : 0, bhi_n = D > 2 ? LVB(3) : 0;
+      int bq = (D > 1 ? LVB(1) : 0) + t;
       double cu = 0.0, cw = 0.0, cv = 0.0;
       int cp = 0;
       if (bq < bhi) {
@@ -586,7 +600,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         cp = c_par(bq);
       }
       for (int L = 1; L < D; ++L) {  // level L is [bq - t, bhi), level L + 1 is [bhi, bhi_n)
-        const int bhi_nn = L + 3 <= D ? lv[L + 3] : 0;
+        const int bhi_nn = L + 3 <= D ? LVB(L + 3) : 0;
         const int nq = bhi + t;
         double nu = 0.0, nw = 0.0, nv = 0.0;
         int np = 0;
@@ -764,7 +778,7 @@ static IntervalFn interval_fn(bool fp32, int threads, int slots, bool uni) {
   return fp32 ? interval_fn_s<float, false>(threads, slots) : interval_fn_s<double, false>(threads, slots);
 }
 
-int interval_node_bytes(int nmax) { return lds_node_bytes(nmax); }
+int interval_row_bytes(int nmax) { return lds_row_bytes(nmax); }
 
 hipError_t set_interval_lds(bool fp32, int threads, int slots, bool uni, int lds_bytes) {
   IntervalFn fn = interval_fn(fp32, threads, slots, uni);

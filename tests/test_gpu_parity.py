@@ -113,14 +113,19 @@ def test_config2_ring_100ms():
     assert_spikes_equal(orc, eng, min_count=100)
 
 
-def test_config3_recipe_400_cells():
+@pytest.mark.parametrize("threads", [0, 512])
+def test_config3_recipe_400_cells(threads):
+    """config 3's recipe on 400 cells; threads=512 is the launch shape the full-size workload takes (512 threads,
+    two register slots, 1024-compartment groups)"""
     m = synth.config3(n_cells=400)
-    say("config3 recipe, 400 cells, 20 ms")
-    orc, eng, worst = lockstep(m, range(40, 801, 40))
+    say(f"config3 recipe, 400 cells, 20 ms, group_threads {threads}")
+    orc, eng, worst = lockstep(m, range(40, 801, 40), group_threads=threads)
     assert worst <= 1.0, worst
     assert_spikes_equal(orc, eng, min_count=50)
     info = eng.info()
     assert info["interval_steps"] == 40
+    if threads:
+        assert info["group_threads"] == 512 and info["group_slots"] == 2
 
 
 def test_config5_recipe_60_cells():
