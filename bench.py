@@ -1,6 +1,6 @@
 """Benchmark: compartment-timesteps per second of the fixed-step cable engine on one MI355X.
 
-Workload: config 3 - 50,000 cells with log-uniform 50..1000 compartments (15.86M compartments), hh + km + cahi in
+Workload: config 3 - 50,000 cells with log-uniform 50..1000 compartments (15.93M compartments), hh + km + cahi in
 every compartment, 100 ExpSyn per cell fed by NetCons with delays U(1, 5) ms (1 ms minimum-delay interval, 40 steps
 of 0.025 ms) and 5 Hz Poisson background per synapse. Synthetic, seeded inputs (synth.config3).
 
@@ -9,6 +9,7 @@ threshold detection, and the interval's spike fan-out). Inputs are resident in H
 The main line reports the FP64 path; the FP32-mechanism path is reported beside it.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -18,6 +19,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP64 vector peak: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops (FMA) x 2.4 GHz
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic FP64 work per compartment-step of config 3 (hh, km, cahi rates and gates, currents, assembly and the
+# tree solve): about 500 lane operations, each exponential or divide counted as the operations it takes
+FLOPS_PER_COMP_STEP = 500.0
+PROFILE = os.path.join(ROOT, "profiles", "cn_interval_config3_traffic.json")
 
 
 def bytes_per_step(m, fp32: bool) -> float:
@@ -33,6 +40,28 @@ def bytes_per_step(m, fp32: bool) -> float:
             b += m.mechs[name].count(n) * 2 * s * k
     b += m.n_syn * (2 * s + 12)
     return float(b)
+
+
+def kernel_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for f in ("cn_kernels.hip", "cn_internal.h", "cn_host.cpp"):
+        with open(os.path.join(ROOT, "paper_1901_10975_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(precision: str):
+    """HBM bytes per interval launch from the committed counter passes, or None when the kernel sources changed
+    since they were taken"""
+    try:
+        with open(PROFILE) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != kernel_sources_sha256():
+        return None
+    k = rec.get("kernels", {}).get(precision)
+    return None if k is None else float(k["traffic_bytes"])
 
 
 def run_gpu(m, precision, steps, warmup, log):
@@ -139,7 +168,11 @@ def main():
 
     bps = bytes_per_step(m, False)
     per_launch = bps * r64["M"]
-    achieved = per_launch / (r64["kernel_ms"] * 1e-3) / 1e9
+    kern_s = r64["kernel_ms"] * 1e-3
+    eff_gbs = per_launch / kern_s / 1e9  # the per-step method's bytes at this rate
+    flops_launch = FLOPS_PER_COMP_STEP * m.n_comp * r64["M"]
+    achieved = flops_launch / kern_s / 1e12
+    traffic = profiled_traffic("fp64")
     out = {
         "metric": "compartment-timesteps/sec at 50k cells (FP64 vs FP32-mech); HBM GB/s fraction",
         "value": r64["value"],
@@ -157,18 +190,24 @@ def main():
                                "100 ExpSyn/cell, NetCon delay U(1,5) ms, Poisson 5 Hz, dt 0.025 ms; one step = one "
                                "1 ms min-delay interval (40 time steps)" % m.n_comp,
                    "n_cells": m.n_cells, "n_comp": m.n_comp, "n_syn": m.n_syn, "interval_steps": r64["M"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        # The interval kernel keeps a group's potentials, states and constants on chip for all M steps, so it moves
+        # far fewer HBM bytes than the per-step method: the bound is FP64 vector arithmetic and the latency of the
+        # tree sweeps, not HBM. traffic = measured HBM bytes per launch (calibrated counters).
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "cn_interval<%d,%d,double>" % (r64["info"]["group_threads"], r64["info"]["group_slots"]),
-                     "kernel_ms": r64["kernel_ms"],
-                     "algorithmic_bytes_per_launch": per_launch},
+                     "kernel_ms": r64["kernel_ms"], "flops_per_launch": flops_launch,
+                     "measured_hbm_GBs": None if traffic is None else traffic / kern_s / 1e9,
+                     "effective_hbm_GBs": eff_gbs, "effective_hbm_frac": eff_gbs / HBM_PEAK_GBS,
+                     "per_step_method_bytes_per_launch": per_launch},
     }
     if r32 is not None:
         bps32 = bytes_per_step(m, True)
         out["fp32_mech"] = {"value": r32["value"], "ms_per_step": r32["wall"] / args.steps * 1e3,
                             "kernel_ms": r32["kernel_ms"],
                             "speedup_vs_fp64": r32["value"] / r64["value"],
-                            "effective_GBs": bps32 * r32["M"] / (r32["kernel_ms"] * 1e-3) / 1e9}
+                            "effective_GBs": bps32 * r32["M"] / (r32["kernel_ms"] * 1e-3) / 1e9,
+                            "traffic": profiled_traffic("fp32_mech")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, log)
     print(json.dumps(out), flush=True)
