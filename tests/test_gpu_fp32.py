@@ -1,0 +1,85 @@
+"""FP32-mechanism path (reading R12) against the FP64 oracle: every spike of the oracle is matched by the same cell's
+spike of the same rank at most one step away (and no extra spikes), and the voltage deviation is bounded. The
+deviations measured here are the figures stated for each config."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1901_10975_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _run(m, checkpoints, cells=None, **kw):
+    from paper_1901_10975_amd import cn
+    orc = O.OracleSim(m, n_threads=16)
+    eng = cn.Engine(m, precision="fp32_mech", **kw)
+    nodes = None if cells is None else np.concatenate(
+        [np.arange(m.cell_offset[c], m.cell_offset[c + 1]) for c in cells])
+    linf, med = 0.0, []
+    for n in checkpoints:
+        orc.run_to_step(n)
+        eng.run_to_step(n)
+        vo, vg = orc.v(), eng.voltages()
+        if nodes is not None:
+            vo, vg = vo[nodes], vg[nodes]
+        d = np.abs(vo - vg)
+        linf = max(linf, float(d.max()))
+        med.append(float(np.median(d)))
+    return orc, eng, linf, float(np.median(med))
+
+
+def _spike_steps_within_one(orc, eng, cells):
+    go, so, _ = orc.spikes()
+    gg, sg, _ = eng.spikes()
+    worst, n = 0, 0
+    for c in cells:
+        a, b = so[go == c], sg[gg == c]
+        assert a.size == b.size, (c, a, b)
+        if a.size:
+            worst = max(worst, int(np.abs(a - b).max()))
+            n += a.size
+    assert worst <= 1, worst
+    return n, worst
+
+
+def test_config4_fp32_mech_100ms():
+    """config 4: config 2's network in the FP32-mechanism path, 100 ms, errors on cells 0-499"""
+    m = synth.config4()
+    cells = np.arange(500)
+    say("config4 fp32_mech 100 ms")
+    orc, eng, linf, med = _run(m, list(range(400, 4001, 400)), cells=cells)
+    n, worst = _spike_steps_within_one(orc, eng, cells)
+    say(f"  cells 0-499: {n} spikes, max |step difference| {worst}, voltage Linf {linf:.3g} mV, median {med:.3g} mV")
+    assert n >= 1000
+    assert med < 1e-3
+    assert linf < 50.0  # a spike one step early or late moves v by tens of mV during the upstroke
+
+
+@pytest.mark.parametrize("threads", [0, 512])
+def test_config3_recipe_fp32_mech(threads):
+    m = synth.config3(n_cells=400)
+    cells = np.arange(m.n_cells)
+    say(f"config3 recipe fp32_mech, 400 cells, 20 ms, group_threads {threads}")
+    orc, eng, linf, med = _run(m, list(range(40, 801, 40)), group_threads=threads)
+    n, worst = _spike_steps_within_one(orc, eng, cells)
+    say(f"  {n} spikes, max |step difference| {worst}, voltage Linf {linf:.3g} mV, median {med:.3g} mV")
+    assert n >= 50
+    assert med < 1e-3
+
+
+def test_config5_recipe_fp32_mech():
+    m = synth.config5(n_cells=60)
+    cells = np.arange(m.n_cells)
+    say("config5 recipe fp32_mech, 60 cells, 10 ms")
+    orc, eng, linf, med = _run(m, list(range(20, 401, 20)))
+    n, worst = _spike_steps_within_one(orc, eng, cells)
+    say(f"  {n} spikes, max |step difference| {worst}, voltage Linf {linf:.3g} mV, median {med:.3g} mV")
+    assert med < 1e-3

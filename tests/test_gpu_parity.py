@@ -273,3 +273,22 @@ def test_full_size_config3_first_interval_sampled():
     go, so, _ = orc.spikes()
     assert np.array_equal(cells[go], gg[keep]) and np.array_equal(so, sg[keep])
     assert np.all(np.isfinite(v))
+
+
+def test_full_size_config5_first_interval_sampled():
+    """config 5 at full size (200,000 cells, about 127M compartments, 20-step interval, 512-thread groups of up to
+    2048 compartments): within the first interval each sampled cell evolves alone, so the oracle computes it alone"""
+    m = synth.config5()
+    say(f"config5 full size: {m.n_cells} cells, {m.n_comp} compartments; first interval, 100 sampled cells")
+    eng = _engine(m)
+    eng.run_to_step(20)
+    assert eng.info()["interval_steps"] == 20
+    v = eng.voltages()
+    rng = np.random.default_rng(1)
+    cells = np.sort(rng.choice(m.n_cells, 100, replace=False))
+    sub = synth.subset_cells(m, cells)
+    orc = O.OracleSim(sub, n_threads=THREADS)
+    orc.run_to_step(20)
+    nodes = np.concatenate([np.arange(m.cell_offset[c], m.cell_offset[c + 1]) for c in cells])
+    assert vrel(v[nodes], orc.v()) <= VTOL
+    assert np.all(np.isfinite(v))
