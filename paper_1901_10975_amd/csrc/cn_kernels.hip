@@ -197,12 +197,13 @@ __device__ __forceinline__ void tri_node(int q, const TriIn &x, int zero, double
                                          double *Q_l) {
   double d = x.d, rhs = x.r;
   gather_children(x.ch, zero, P_l, Q_l, d, rhs);
+  const double adv = x.a * x.dv;  // off the dependency chain
   const double ri = rcp64(d);
   const double w = ri * x.b, u = ri * rhs;
   w_l[q] = w;
   u_l[q] = u;
-  P_l[q] = x.a * (w + 1.0);
-  Q_l[q] = x.a * (u - x.dv);
+  P_l[q] = fma(x.a, w, x.a);  // a (w + 1)
+  Q_l[q] = fma(x.a, u, -adv);  // a (u - dv)
 }
 
 // ------------------------------------------------------------------------------------------------------------------
@@ -586,48 +587,57 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
       if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
     }
     __syncthreads();
-    // ---- B: substitution, root to leaves: x = u - w x_parent, v += x. A level's u, w, parent and v are final
-    // after the elimination, so each thread loads them one level ahead; after a barrier only x_parent remains.
-    {
-      int bhi = D > 1 ? LVB(2) : 0, bhi_n = D > 2 ? LVB(3) : 0;
-      int bq = (D > 1 ? LVB(1) : 0) + t;
-      double cu = 0.0, cw = 0.0, cv = 0.0;
-      int cp = 0;
-      if (bq < bhi) {
-        cu = u_l[bq];
-        cw = w_l[bq];
-        cv = V_l[bq];
-        cp = c_par(bq);
-      }
-      for (int L = 1; L < D; ++L) {  // level L is [bq - t, bhi), level L + 1 is [bhi, bhi_n)
-        const int bhi_nn = L + 3 <= D ? LVB(L + 3) : 0;
-        const int nq = bhi + t;
-        double nu = 0.0, nw = 0.0, nv = 0.0;
-        int np = 0;
-        if (L + 1 < D && nq < bhi_n) {
-          nu = u_l[nq];
-          nw = w_l[nq];
-          nv = V_l[nq];
-          np = c_par(nq);
+    // ---- B: substitution, root to leaves, v += x, two levels per barrier. A node of the first level of a pass
+    // reads its parent's x: x = u - w x_p. A node of the second level folds its parent's step in and reads its
+    // grandparent's: x = (u - w u_p) - (-w w_p) x_gp. Every term but the x read after the barrier is final once the
+    // elimination is done, so each thread loads (and folds) them one pass ahead.
+    if (D > 1) {
+      // inputs of node q in a pass whose second level starts at mid: x = cu - cw x[cs], v = cv + x
+      auto pass_in = [&](int q, int mid, double &cu, double &cw, double &cv, int &cs) {
+        cu = u_l[q];
+        cw = w_l[q];
+        cv = V_l[q];
+        cs = c_par(q);
+        if (q >= mid) {
+          const double up = u_l[cs], wp = w_l[cs];
+          cs = c_par(cs);
+          cu = fma(-cw, up, cu);
+          cw = -(cw * wp);
         }
-        if (bq < bhi) {
-          const double x = cu - cw * P_l[cp];
+      };
+      int bmid = LVB(min(2, D)), bend = LVB(min(3, D));
+      int bq = LVB(1) + t;
+      double cu = 0.0, cw = 0.0, cv = 0.0;
+      int cs = 0;
+      if (bq < bend) pass_in(bq, bmid, cu, cw, cv, cs);
+      for (int L0 = 1; L0 < D; L0 += 2) {  // this pass: levels L0 and L0 + 1, nodes [bq - t, bend)
+        const int L1 = L0 + 2;
+        const int nmid = L1 < D ? LVB(min(L1 + 1, D)) : 0, nend = L1 < D ? LVB(min(L1 + 2, D)) : 0;
+        const int nq = bend + t;
+        double nu = 0.0, nw = 0.0, nv = 0.0;
+        int ns = 0;
+        if (nq < nend) pass_in(nq, nmid, nu, nw, nv, ns);
+        if (bq < bend) {
+          const double x = cu - cw * P_l[cs];
           P_l[bq] = x;
           V_l[bq] = cv + x;
         }
-        for (int q2 = bq + T; q2 < bhi; q2 += T) {  // wide levels
-          const double x = u_l[q2] - w_l[q2] * P_l[c_par(q2)];
+        for (int q2 = bq + T; q2 < bend; q2 += T) {  // passes wider than the group's threads
+          double u2, w2, v2;
+          int s2;
+          pass_in(q2, bmid, u2, w2, v2, s2);
+          const double x = u2 - w2 * P_l[s2];
           P_l[q2] = x;
-          V_l[q2] += x;
+          V_l[q2] = v2 + x;
         }
         __syncthreads();
         bq = nq;
-        bhi = bhi_n;
-        bhi_n = bhi_nn;
+        bmid = nmid;
+        bend = nend;
         cu = nu;
         cw = nw;
         cv = nv;
-        cp = np;
+        cs = ns;
       }
     }
   }
