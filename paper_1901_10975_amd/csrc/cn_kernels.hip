@@ -587,36 +587,44 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
       if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
     }
     __syncthreads();
-    // ---- B: substitution, root to leaves, v += x, two levels per barrier. A node of the first level of a pass
-    // reads its parent's x: x = u - w x_p. A node of the second level folds its parent's step in and reads its
-    // grandparent's: x = (u - w u_p) - (-w w_p) x_gp. Every term but the x read after the barrier is final once the
-    // elimination is done, so each thread loads (and folds) them one pass ahead.
+    // ---- B: substitution, root to leaves, v += x, BL levels per barrier. A node of the first level of a pass reads
+    // its parent's x: x = u - w x_p. A node j levels deeper folds the steps of its j nearest ancestors into its
+    // coefficients, x = cu - cw x_a with a its (j+1)-th ancestor (cu <- cu - cw u_p, cw <- -cw w_p, p <- parent of
+    // p), and reads x_a, which a previous pass computed. Every term but that x is final once the elimination is
+    // done, so each thread loads and folds them one pass ahead.
     if (D > 1) {
-      // inputs of node q in a pass whose second level starts at mid: x = cu - cw x[cs], v = cv + x
-      auto pass_in = [&](int q, int mid, double &cu, double &cw, double &cv, int &cs) {
+      constexpr int BL = 3;
+      // inputs of node q in a pass whose deeper levels start at m1, m2: x = cu - cw x[cs], v = cv + x
+      auto pass_in = [&](int q, int m1, int m2, double &cu, double &cw, double &cv, int &cs) {
         cu = u_l[q];
         cw = w_l[q];
         cv = V_l[q];
         cs = c_par(q);
-        if (q >= mid) {
+        const int j = (q >= m1) + (q >= m2);
+        for (int i = 0; i < j; ++i) {
           const double up = u_l[cs], wp = w_l[cs];
           cs = c_par(cs);
           cu = fma(-cw, up, cu);
           cw = -(cw * wp);
         }
       };
-      int bmid = LVB(min(2, D)), bend = LVB(min(3, D));
+      int bm1 = LVB(min(2, D)), bm2 = LVB(min(3, D)), bend = LVB(min(1 + BL, D));
       int bq = LVB(1) + t;
       double cu = 0.0, cw = 0.0, cv = 0.0;
       int cs = 0;
-      if (bq < bend) pass_in(bq, bmid, cu, cw, cv, cs);
-      for (int L0 = 1; L0 < D; L0 += 2) {  // this pass: levels L0 and L0 + 1, nodes [bq - t, bend)
-        const int L1 = L0 + 2;
-        const int nmid = L1 < D ? LVB(min(L1 + 1, D)) : 0, nend = L1 < D ? LVB(min(L1 + 2, D)) : 0;
+      if (bq < bend) pass_in(bq, bm1, bm2, cu, cw, cv, cs);
+      for (int L0 = 1; L0 < D; L0 += BL) {  // this pass: levels L0 .. L0 + BL - 1, nodes [bq - t, bend)
+        const int L1 = L0 + BL;
+        int nm1 = 0, nm2 = 0, nend = 0;
+        if (L1 < D) {
+          nm1 = LVB(min(L1 + 1, D));
+          nm2 = LVB(min(L1 + 2, D));
+          nend = LVB(min(L1 + BL, D));
+        }
         const int nq = bend + t;
         double nu = 0.0, nw = 0.0, nv = 0.0;
         int ns = 0;
-        if (nq < nend) pass_in(nq, nmid, nu, nw, nv, ns);
+        if (nq < nend) pass_in(nq, nm1, nm2, nu, nw, nv, ns);
         if (bq < bend) {
           const double x = cu - cw * P_l[cs];
           P_l[bq] = x;
@@ -625,14 +633,15 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         for (int q2 = bq + T; q2 < bend; q2 += T) {  // passes wider than the group's threads
           double u2, w2, v2;
           int s2;
-          pass_in(q2, bmid, u2, w2, v2, s2);
+          pass_in(q2, bm1, bm2, u2, w2, v2, s2);
           const double x = u2 - w2 * P_l[s2];
           P_l[q2] = x;
           V_l[q2] = v2 + x;
         }
         __syncthreads();
         bq = nq;
-        bmid = nmid;
+        bm1 = nm1;
+        bm2 = nm2;
         bend = nend;
         cu = nu;
         cw = nw;
