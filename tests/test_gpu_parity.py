@@ -137,6 +137,25 @@ def test_config5_recipe_60_cells():
     assert eng.info()["interval_steps"] == 20
 
 
+@pytest.mark.parametrize("threads", [0, 512])
+def test_per_compartment_parameters(threads):
+    """density-mechanism parameters that differ between compartments (the per-node parameter table path), over
+    25 ms of an active network (weights x4): beyond that, rounding differences grow chaotically on this network"""
+    m = synth.config2(n_cells=120, n_comp=150, seed=31)
+    rng = np.random.default_rng(31)
+    hh = m.mechs["hh"]
+    k = m.n_comp if hh.node is None else hh.node.size
+    hh.params["gnabar"] = rng.uniform(0.08, 0.16, k)
+    hh.params["gkbar"] = rng.uniform(0.02, 0.05, k)
+    hh.params["gl"] = rng.uniform(1e-4, 5e-4, k)
+    hh.params["el"] = rng.uniform(-60.0, -50.0, k)
+    m.nc_weight = m.nc_weight * 4
+    say(f"per-compartment parameters, group_threads {threads}")
+    orc, eng, worst = lockstep(m, range(100, 1001, 100), group_threads=threads)
+    assert worst <= 1.0, worst
+    assert_spikes_equal(orc, eng, min_count=20)
+
+
 def test_irregular_run_lengths_and_graph_off():
     m = synth.config2(n_cells=80, n_comp=60, seed=21)
     m.nc_weight = m.nc_weight * 10

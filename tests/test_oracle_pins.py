@@ -103,6 +103,26 @@ def test_passive_chain_discrete_steady_state():
     np.testing.assert_allclose(sim.v(), expect, rtol=0, atol=1e-10 * np.abs(expect - e).max())
 
 
+def test_passive_cable_converges_second_order_to_continuous():
+    """sealed cable of length l with current I into its end compartment converges, at the compartment centres, to
+    the continuous V(x) = I r_a lambda cosh((l - x)/lambda) / sinh(l/lambda) with error O(h^2)"""
+    ell, diam, ra, g, e, amp = 600.0, 1.0, 100.0, 1e-4, -65.0, 0.05  # um, um, ohm cm, S/cm^2, mV, nA
+    lam = np.sqrt((1.0 / g) * (diam * 1e-4) / (4.0 * ra))  # cm
+    r_a = 4.0 * ra / (np.pi * (diam * 1e-4) ** 2)  # ohm / cm
+    errs = []
+    for N in (15, 30, 60):
+        h = ell / N
+        m = TM.make([TM.chain(N)], np.pi * diam * h, TM.ri_uniform(diam, h, ra),
+                    {"pas": TM.pas(None, g, e), "iclamp": TM.iclamp([0], amp)}, dt=10.0)
+        sim = O.OracleSim(m)
+        sim.run_to_step(600)
+        x = (np.arange(N) + 0.5) * h * 1e-4  # cm
+        V = 1e3 * amp * 1e-9 * r_a * lam * np.cosh((ell * 1e-4 - x) / lam) / np.sinh(ell * 1e-4 / lam)  # mV
+        errs.append(np.abs(sim.v() - e - V).max())
+    assert errs[2] < 1e-3 * V.max()
+    assert 3.6 < errs[0] / errs[1] < 4.4 and 3.6 < errs[1] / errs[2] < 4.4, errs
+
+
 def test_passive_tree_steady_state_dense_solve():
     """steady state of a random passive tree equals the dense solve of (G_m + G_axial) u = I"""
     rng = np.random.default_rng(7)
@@ -243,6 +263,82 @@ def test_hh_isi_against_rk4():
         errs.append(abs(np.diff(t)[1:].mean() - isi_ref))
     assert errs[0] / isi_ref < 0.03
     assert 0.3 < errs[1] / errs[0] < 0.7  # first-order convergence of the fixed step
+
+
+def _rk4_fires(J, t_end=30.0, h=2.5e-3):
+    """for each step current J (uA/cm^2, from rest at -65 mV): does the continuous HH model reach 0 mV?"""
+    def vt(x, y):
+        small = np.abs(x / y) < 1e-9
+        return np.where(small, y * (1 - x / y / 2), x / np.expm1(np.where(small, 1.0, x / y)))
+
+    def rates(v):
+        return (0.1 * vt(-(v + 40), 10), 4 * np.exp(-(v + 65) / 18), 0.07 * np.exp(-(v + 65) / 20),
+                1 / (np.exp(-(v + 35) / 10) + 1), 0.01 * vt(-(v + 55), 10), 0.125 * np.exp(-(v + 65) / 80))
+
+    def f(v, mm, hh, nn):
+        am, bm, ah, bh, an, bn = rates(v)
+        i = 120 * mm ** 3 * hh * (v - 50) + 36 * nn ** 4 * (v + 77) + 0.3 * (v + 54.3)
+        return J - i, am * (1 - mm) - bm * mm, ah * (1 - hh) - bh * hh, an * (1 - nn) - bn * nn
+
+    am, bm, ah, bh, an, bn = rates(np.full(J.shape, -65.0))
+    y = [np.full(J.shape, -65.0), am / (am + bm), ah / (ah + bh), an / (an + bn)]
+    fired = np.zeros(J.shape, bool)
+    for _ in range(int(round(t_end / h))):
+        k1 = f(*y)
+        k2 = f(*[a + 0.5 * h * b for a, b in zip(y, k1)])
+        k3 = f(*[a + 0.5 * h * b for a, b in zip(y, k2)])
+        k4 = f(*[a + h * b for a, b in zip(y, k3)])
+        y = [a + h / 6 * (b1 + 2 * b2 + 2 * b3 + b4) for a, b1, b2, b3, b4 in zip(y, k1, k2, k3, k4)]
+        fired |= y[0] >= 0.0
+    return fired
+
+
+def _oracle_fires(J, t_end=30.0, dt=0.025):
+    return np.array([_oracle_spike_times(j, t_end, dt).size > 0 for j in J])
+
+
+def _threshold(fires, lo, hi, rounds=3, n=17):
+    for _ in range(rounds):
+        J = np.linspace(lo, hi, n)
+        f = fires(J)
+        assert not f[0] and f[-1]
+        k = int(np.argmax(f))
+        lo, hi = J[k - 1], J[k]
+    return 0.5 * (lo + hi)
+
+
+def test_hh_step_current_threshold_against_rk4():
+    """the smallest step current from rest that fires the oracle's HH compartment (dt 0.025 ms) is within 2 % of
+    that of the continuous model integrated by RK4"""
+    ref = _threshold(_rk4_fires, 0.5, 10.0)
+    got = _threshold(_oracle_fires, 0.5, 10.0)
+    assert 1.0 < ref < 8.0
+    assert abs(got - ref) / ref < 0.02, (got, ref)
+
+
+def test_gate_update_is_exponential_at_clamped_voltage():
+    """with a huge capacitance holding v after a one-step current pulse moved it from -65 to about -30 mV, every HH
+    gate follows x_{n+1} - x_inf = r (x_n - x_inf) with one constant r = exp(-dt/tau) (reading R3), and settles at
+    a fixed point"""
+    A, cm, dt = 1000.0, 1e12, 0.025
+    c = 1e-3 * cm / dt  # S/cm^2
+    amp = c * 35.0 * A / 100.0  # nA: +35 mV in the first step
+    m = TM.make([[-1]], A, 0.0, {"hh": TM.hh(), "iclamp": TM.iclamp([0], amp, dl=0.0, dur=dt)}, cm=cm, dt=dt)
+    sim = O.OracleSim(m)
+    xs = []
+    for n in range(1, 200):
+        sim.run_to_step(n)
+        st = sim.states()
+        xs.append([st["hh_m"][0], st["hh_h"][0], st["hh_n"][0]])
+    assert abs(sim.v()[0] + 30.0) < 1e-3
+    xs = np.array(xs)
+    for g in range(3):
+        dx = np.diff(xs[:, g])
+        keep = np.abs(dx[:-1]) > 1e-9
+        r = dx[1:][keep] / dx[:-1][keep]
+        assert r.size > 10
+        assert 0.0 < r[0] < 1.0
+        assert np.abs(r - r[0]).max() < 1e-6 * max(1.0, 1.0 / (1.0 - r[0]))
 
 
 # --------------------------------------------------------------------------------------------------------------
