@@ -17,6 +17,8 @@
 // of Sec. 2, here on one device).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cn_internal.h"
 
 namespace cn {
@@ -170,14 +172,15 @@ struct TriIn {
 
 // subtract the children's contributions (children c0 .. c0 + count - 1 on the level below) from d and rhs, in child
 // order. The first four are read unconditionally, an absent child from the zero entry `zero` of the rows (x - 0
-// is x exactly), so one LDS round trip serves most nodes without per-child masking.
+// is x exactly), so one LDS round trip serves most nodes without per-child masking. Child k is read at base + k
+// with base c0, or zero - k when absent, so that k stays an immediate offset.
 __device__ __forceinline__ void gather_children(uint32_t ch, int zero, const double *P_l, const double *Q_l,
                                                 double &d, double &rhs) {
   const int c0 = (int)(ch & 0xFFFFu), cn = (int)(ch >> 16);
-  const int i0 = cn > 0 ? c0 : zero, i1 = cn > 1 ? c0 + 1 : zero, i2 = cn > 2 ? c0 + 2 : zero,
-            i3 = cn > 3 ? c0 + 3 : zero;
-  const double p0 = P_l[i0], p1 = P_l[i1], p2 = P_l[i2], p3 = P_l[i3];
-  const double q0 = Q_l[i0], q1 = Q_l[i1], q2 = Q_l[i2], q3 = Q_l[i3];
+  const int i0 = cn > 0 ? c0 : zero, j1 = cn > 1 ? c0 : zero - 1, j2 = cn > 2 ? c0 : zero - 2,
+            j3 = cn > 3 ? c0 : zero - 3;
+  const double p0 = P_l[i0], p1 = P_l[j1 + 1], p2 = P_l[j2 + 2], p3 = P_l[j3 + 3];
+  const double q0 = Q_l[i0], q1 = Q_l[j1 + 1], q2 = Q_l[j2 + 2], q3 = Q_l[j3 + 3];
   d -= p0;
   rhs -= q0;
   d -= p1;
@@ -405,7 +408,6 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
   }
   // level starts, lane L of every wave holding lv[L]: read back with a lane read instead of an LDS round trip
   const int lvr = (t & 63) <= D ? lv[t & 63] : 0;
-  auto LVB = [&](int L) -> int { return D < 64 ? __builtin_amdgcn_readlane(lvr, L) : lv[L]; };
   // synapse terms are staged on chip when the group's synapses fit the rows
   const bool staged = n_syn <= 2 * NMAX;
   __syncthreads();
@@ -547,108 +549,114 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     }
     __syncthreads();
     __builtin_amdgcn_s_setprio(2);
-    // ---- T: elimination, deepest level first, one thread per node of the level. A level's own inputs are final
-    // before it starts, so each thread loads them one level ahead; after a barrier only the children's
-    // contributions remain to be read. Level bounds are read two levels ahead.
-    int hi = LVB(D), lo = LVB(D - 1), lo_n = D >= 2 ? LVB(D - 2) : 0;
-    int q = lo + t;
-    TriIn cur{};
-    if (q < hi) cur = tri_in(q);
-    for (int L = D - 1; L >= 1; --L) {  // level L is [lo, hi), level L - 1 is [lo_n, lo)
-      const int lo_nn = L >= 2 ? LVB(L - 2) : 0;
-      const int nq = lo_n + t;
-      TriIn nxt{};
-      if (nq < lo) nxt = tri_in(nq);
-      if (q < hi) tri_node(q, cur, NMAX, w_l, u_l, P_l, Q_l);
-      for (int q2 = q + T; q2 < hi; q2 += T) tri_node(q2, tri_in(q2), NMAX, w_l, u_l, P_l, Q_l);  // wide levels
-      __syncthreads();
-      hi = lo;
-      lo = lo_n;
-      lo_n = lo_nn;
-      q = nq;
-      cur = nxt;
-    }
-    // ---- R: roots (level 0 holds the group's cells in order): solve, v update, threshold detection
-    for (; q < hi; q += T) {
-      const TriIn x = q == t ? cur : tri_in(q);
-      double d = x.d, rhs = x.r;
-      gather_children(x.ch, NMAX, P_l, Q_l, d, rhs);
-      const double xs = rhs / d;
-      const double vold = x.dv;
-      const double vnew = vold + xs;
-      P_l[q] = xs;
-      V_l[q] = vnew;
-      const double th = q == t ? theta0 : p.cell_theta[gd.cell_base + q];
-      if (vold < th && th <= vnew) {
-        const int idx = atomicAdd(&misc[1], 1);
-        p.gsp_pack[gd.spk_base + idx] = q | ((s + 1) << 16);
-        p.gsp_frac[gd.spk_base + idx] = (th - vold) / (vnew - vold);
-      }
-      if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
-    }
-    __syncthreads();
-    // ---- B: substitution, root to leaves, v += x, BL levels per barrier. A node of the first level of a pass reads
-    // its parent's x: x = u - w x_p. A node j levels deeper folds the steps of its j nearest ancestors into its
-    // coefficients, x = cu - cw x_a with a its (j+1)-th ancestor (cu <- cu - cw u_p, cw <- -cw w_p, p <- parent of
-    // p), and reads x_a, which a previous pass computed. Every term but that x is final once the elimination is
-    // done, so each thread loads and folds them one pass ahead.
-    if (D > 1) {
-      constexpr int BL = 3;
-      // inputs of node q in a pass whose deeper levels start at m1, m2: x = cu - cw x[cs], v = cv + x
-      auto pass_in = [&](int q, int m1, int m2, double &cu, double &cw, double &cv, int &cs) {
-        cu = u_l[q];
-        cw = w_l[q];
-        cv = V_l[q];
-        cs = c_par(q);
-        const int j = (q >= m1) + (q >= m2);
-        for (int i = 0; i < j; ++i) {
-          const double up = u_l[cs], wp = w_l[cs];
-          cs = c_par(cs);
-          cu = fma(-cw, up, cu);
-          cw = -(cw * wp);
-        }
-      };
-      int bm1 = LVB(min(2, D)), bm2 = LVB(min(3, D)), bend = LVB(min(1 + BL, D));
-      int bq = LVB(1) + t;
-      double cu = 0.0, cw = 0.0, cv = 0.0;
-      int cs = 0;
-      if (bq < bend) pass_in(bq, bm1, bm2, cu, cw, cv, cs);
-      for (int L0 = 1; L0 < D; L0 += BL) {  // this pass: levels L0 .. L0 + BL - 1, nodes [bq - t, bend)
-        const int L1 = L0 + BL;
-        int nm1 = 0, nm2 = 0, nend = 0;
-        if (L1 < D) {
-          nm1 = LVB(min(L1 + 1, D));
-          nm2 = LVB(min(L1 + 2, D));
-          nend = LVB(min(L1 + BL, D));
-        }
-        const int nq = bend + t;
-        double nu = 0.0, nw = 0.0, nv = 0.0;
-        int ns = 0;
-        if (nq < nend) pass_in(nq, nm1, nm2, nu, nw, nv, ns);
-        if (bq < bend) {
-          const double x = cu - cw * P_l[cs];
-          P_l[bq] = x;
-          V_l[bq] = cv + x;
-        }
-        for (int q2 = bq + T; q2 < bend; q2 += T) {  // passes wider than the group's threads
-          double u2, w2, v2;
-          int s2;
-          pass_in(q2, bm1, bm2, u2, w2, v2, s2);
-          const double x = u2 - w2 * P_l[s2];
-          P_l[q2] = x;
-          V_l[q2] = v2 + x;
-        }
+    // the sweeps, with level starts read from lane registers when the group has fewer than 64 levels
+    auto sweeps = [&](auto lane_bounds) {
+      constexpr bool LR = decltype(lane_bounds)::value;
+      auto LVB = [&](int L) -> int { return LR ? __builtin_amdgcn_readlane(lvr, L) : lv[L]; };
+      // ---- T: elimination, deepest level first, one thread per node of the level. A level's own inputs are final
+      // before it starts, so each thread loads them one level ahead; after a barrier only the children's
+      // contributions remain to be read.
+      int hi = LVB(D), lo = LVB(D - 1), lo_n = D >= 2 ? LVB(D - 2) : 0;
+      int q = lo + t;
+      TriIn cur{};
+      if (q < hi) cur = tri_in(q);
+      for (int L = D - 1; L >= 1; --L) {  // level L is [lo, hi), level L - 1 is [lo_n, lo)
+        const int lo_nn = L >= 2 ? LVB(L - 2) : 0;
+        const int nq = lo_n + t;
+        const TriIn nxt = tri_in(min(nq, N - 1));  // lanes past the level read the group's last node and ignore it
+        if (q < hi) tri_node(q, cur, NMAX, w_l, u_l, P_l, Q_l);
+        for (int q2 = q + T; q2 < hi; q2 += T) tri_node(q2, tri_in(q2), NMAX, w_l, u_l, P_l, Q_l);  // wide levels
         __syncthreads();
-        bq = nq;
-        bm1 = nm1;
-        bm2 = nm2;
-        bend = nend;
-        cu = nu;
-        cw = nw;
-        cv = nv;
-        cs = ns;
+        hi = lo;
+        lo = lo_n;
+        lo_n = lo_nn;
+        q = nq;
+        cur = nxt;
       }
-    }
+      // ---- R: roots (level 0 holds the group's cells in order): solve, v update, threshold detection
+      for (; q < hi; q += T) {
+        const TriIn x = q == t ? cur : tri_in(q);
+        double d = x.d, rhs = x.r;
+        gather_children(x.ch, NMAX, P_l, Q_l, d, rhs);
+        const double xs = rhs / d;
+        const double vold = x.dv;
+        const double vnew = vold + xs;
+        P_l[q] = xs;
+        V_l[q] = vnew;
+        const double th = q == t ? theta0 : p.cell_theta[gd.cell_base + q];
+        if (vold < th && th <= vnew) {
+          const int idx = atomicAdd(&misc[1], 1);
+          p.gsp_pack[gd.spk_base + idx] = q | ((s + 1) << 16);
+          p.gsp_frac[gd.spk_base + idx] = (th - vold) / (vnew - vold);
+        }
+        if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
+      }
+      __syncthreads();
+      // ---- B: substitution, root to leaves, v += x, BL levels per barrier. A node of the first level of a pass reads
+      // its parent's x: x = u - w x_p. A node j levels deeper folds the steps of its j nearest ancestors into its
+      // coefficients, x = cu - cw x_a with a its (j+1)-th ancestor (cu <- cu - cw u_p, cw <- -cw w_p, p <- parent of
+      // p), and reads x_a, which a previous pass computed. Every term but that x is final once the elimination is
+      // done, so each thread loads and folds them one pass ahead.
+      if (D > 1) {
+        constexpr int BL = 3;
+        // inputs of node q in a pass whose deeper levels start at m1, m2: x = cu - cw x[cs], v = cv + x
+        auto pass_in = [&](int q, int m1, int m2, double &cu, double &cw, double &cv, int &cs) {
+          cu = u_l[q];
+          cw = w_l[q];
+          cv = V_l[q];
+          cs = c_par(q);
+          const int j = (q >= m1) + (q >= m2);
+          for (int i = 0; i < j; ++i) {
+            const double up = u_l[cs], wp = w_l[cs];
+            cs = c_par(cs);
+            cu = fma(-cw, up, cu);
+            cw = -(cw * wp);
+          }
+        };
+        int bm1 = LVB(min(2, D)), bm2 = LVB(min(3, D)), bend = LVB(min(1 + BL, D));
+        int bq = LVB(1) + t;
+        double cu = 0.0, cw = 0.0, cv = 0.0;
+        int cs = 0;
+        if (bq < bend) pass_in(bq, bm1, bm2, cu, cw, cv, cs);
+        for (int L0 = 1; L0 < D; L0 += BL) {  // this pass: levels L0 .. L0 + BL - 1, nodes [bq - t, bend)
+          const int L1 = L0 + BL;
+          int nm1 = 0, nm2 = 0, nend = 0;
+          if (L1 < D) {
+            nm1 = LVB(min(L1 + 1, D));
+            nm2 = LVB(min(L1 + 2, D));
+            nend = LVB(min(L1 + BL, D));
+          }
+          const int nq = bend + t;
+          double nu = 0.0, nw = 0.0, nv = 0.0;
+          int ns = 0;
+          if (nq < nend) pass_in(nq, nm1, nm2, nu, nw, nv, ns);
+          if (bq < bend) {
+            const double x = cu - cw * P_l[cs];
+            P_l[bq] = x;
+            V_l[bq] = cv + x;
+          }
+          for (int q2 = bq + T; q2 < bend; q2 += T) {  // passes wider than the group's threads
+            double u2, w2, v2;
+            int s2;
+            pass_in(q2, bm1, bm2, u2, w2, v2, s2);
+            const double x = u2 - w2 * P_l[s2];
+            P_l[q2] = x;
+            V_l[q2] = v2 + x;
+          }
+          __syncthreads();
+          bq = nq;
+          bm1 = nm1;
+          bm2 = nm2;
+          bend = nend;
+          cu = nu;
+          cw = nw;
+          cv = nv;
+          cs = ns;
+        }
+      }
+    };
+    if (D < 64) sweeps(std::true_type{});
+    else sweeps(std::false_type{});
   }
 
   // ---- epilogue: potentials and states back to global memory; the chunk's spikes (count in gsp_cnt) are recorded
