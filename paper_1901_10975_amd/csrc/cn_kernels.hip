@@ -170,17 +170,22 @@ struct TriIn {
   uint32_t ch;
 };
 
-// subtract the children's contributions (children c0 .. c0 + count - 1 on the level below) from d and rhs, in child
-// order. The first four are read unconditionally, an absent child from the zero entry `zero` of the rows (x - 0
-// is x exactly), so one LDS round trip serves most nodes without per-child masking. Child k is read at base + k
-// with base c0, or zero - k when absent, so that k stays an immediate offset.
-__device__ __forceinline__ void gather_children(uint32_t ch, int zero, const double *P_l, const double *Q_l,
+// Subtract the children's contributions from d and rhs, in child order. `ch` holds the byte offset of the first
+// child (its position times 8) in the low 16 bits and the child count in the high 16; `zero8` is the byte offset of
+// the rows' zero entry. The first four children are read unconditionally, an absent one from the zero entry (x - 0
+// is x exactly), so one LDS round trip serves most nodes. Child k is read at base + 8k, with base the first child's
+// offset or zero8 - 8k when absent: 8k stays the instruction's immediate offset.
+__device__ __forceinline__ double lds_at(const double *row, int byte_off) {
+  return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(row) + byte_off);
+}
+__device__ __forceinline__ void gather_children(uint32_t ch, int zero8, const double *P_l, const double *Q_l,
                                                 double &d, double &rhs) {
   const int c0 = (int)(ch & 0xFFFFu), cn = (int)(ch >> 16);
-  const int i0 = cn > 0 ? c0 : zero, j1 = cn > 1 ? c0 : zero - 1, j2 = cn > 2 ? c0 : zero - 2,
-            j3 = cn > 3 ? c0 : zero - 3;
-  const double p0 = P_l[i0], p1 = P_l[j1 + 1], p2 = P_l[j2 + 2], p3 = P_l[j3 + 3];
-  const double q0 = Q_l[i0], q1 = Q_l[j1 + 1], q2 = Q_l[j2 + 2], q3 = Q_l[j3 + 3];
+  int b0 = cn > 0 ? c0 : zero8, b1 = cn > 1 ? c0 : zero8 - 8, b2 = cn > 2 ? c0 : zero8 - 16,
+      b3 = cn > 3 ? c0 : zero8 - 24;
+  asm volatile("" : "+v"(b1), "+v"(b2), "+v"(b3));  // keep the selects on the bases
+  const double p0 = lds_at(P_l, b0), p1 = lds_at(P_l, b1 + 8), p2 = lds_at(P_l, b2 + 16), p3 = lds_at(P_l, b3 + 24);
+  const double q0 = lds_at(Q_l, b0), q1 = lds_at(Q_l, b1 + 8), q2 = lds_at(Q_l, b2 + 16), q3 = lds_at(Q_l, b3 + 24);
   d -= p0;
   rhs -= q0;
   d -= p1;
@@ -189,17 +194,17 @@ __device__ __forceinline__ void gather_children(uint32_t ch, int zero, const dou
   rhs -= q2;
   d -= p3;
   rhs -= q3;
-  for (int c = c0 + 4; c < c0 + cn; ++c) {
-    d -= P_l[c];
-    rhs -= Q_l[c];
+  for (int c = c0 + 32; c < c0 + 8 * cn; c += 8) {
+    d -= lds_at(P_l, c);
+    rhs -= lds_at(Q_l, c);
   }
 }
 
 // one node of the elimination: gather the children's contributions, then publish this node's own
-__device__ __forceinline__ void tri_node(int q, const TriIn &x, int zero, double *w_l, double *u_l, double *P_l,
+__device__ __forceinline__ void tri_node(int q, const TriIn &x, int zero8, double *w_l, double *u_l, double *P_l,
                                          double *Q_l) {
   double d = x.d, rhs = x.r;
-  gather_children(x.ch, zero, P_l, Q_l, d, rhs);
+  gather_children(x.ch, zero8, P_l, Q_l, d, rhs);
   const double adv = x.a * x.dv;  // off the dependency chain
   const double ri = rcp64(d);
   const double w = ri * x.b, u = ri * rhs;
@@ -361,7 +366,12 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
   auto c_b = [&](int q) { return CL ? b_l[q] : p.nrec[nb + q].b; };
   auto c_k = [&](int q) { return CL ? k_l[q] : p.nrec[nb + q].k; };
   auto c_par = [&](int q) { return CL ? par_l[q] : p.nidx[nb + q].par; };
-  auto c_ch = [&](int q) { return CL ? ch_l[q] : p.nidx[nb + q].ch; };
+  // children: first child as a byte offset (position times 8) | count << 16
+  auto c_ch = [&](int q) {
+    if (CL) return ch_l[q];
+    const uint32_t c = p.nidx[nb + q].ch;
+    return ((c & 0xFFFFu) << 3) | (c & 0xFFFF0000u);
+  };
   auto tri_in = [&](int q) { return TriIn{c_a(q), c_b(q), w_l[q], u_l[q], Q_l[q], c_ch(q)}; };
   auto prm = [&](int col, int64_t i) -> double { return UNI ? cst[C_PRM + col] : p.prm[col * p.n_nodes_total + i]; };
   StRec<S> *st = static_cast<StRec<S> *>(p.st);
@@ -376,7 +386,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
       b_l[q] = nr.b;
       k_l[q] = nr.k;
       par_l[q] = nx.par;
-      ch_l[q] = nx.ch;
+      ch_l[q] = ((nx.ch & 0xFFFFu) << 3) | (nx.ch & 0xFFFF0000u);
     }
   }
   // per-slot registers for the whole chunk: channel states, parent, counts-and-flags, first synapse
@@ -564,8 +574,8 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         const int lo_nn = L >= 2 ? LVB(L - 2) : 0;
         const int nq = lo_n + t;
         const TriIn nxt = tri_in(min(nq, N - 1));  // lanes past the level read the group's last node and ignore it
-        if (q < hi) tri_node(q, cur, NMAX, w_l, u_l, P_l, Q_l);
-        for (int q2 = q + T; q2 < hi; q2 += T) tri_node(q2, tri_in(q2), NMAX, w_l, u_l, P_l, Q_l);  // wide levels
+        if (q < hi) tri_node(q, cur, NMAX * 8, w_l, u_l, P_l, Q_l);
+        for (int q2 = q + T; q2 < hi; q2 += T) tri_node(q2, tri_in(q2), NMAX * 8, w_l, u_l, P_l, Q_l);  // wide levels
         __syncthreads();
         hi = lo;
         lo = lo_n;
@@ -577,8 +587,8 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
       for (; q < hi; q += T) {
         const TriIn x = q == t ? cur : tri_in(q);
         double d = x.d, rhs = x.r;
-        gather_children(x.ch, NMAX, P_l, Q_l, d, rhs);
-        const double xs = rhs / d;
+        gather_children(x.ch, NMAX * 8, P_l, Q_l, d, rhs);
+        const double xs = rhs * rcp64(d);
         const double vold = x.dv;
         const double vnew = vold + xs;
         P_l[q] = xs;
