@@ -424,16 +424,17 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
   // everything but the compartments' assembly is latency-bound and runs at the higher wave priority
   __builtin_amdgcn_s_setprio(2);
 
-  for (int64_t n = n_begin; n < n_end; ++n) {
-    const int s = (int)(n - ival * M);
-    // ---- background-event bits for a block of four steps (one Philox call gives four words)
+  // ---- background-event bits and delivery for step n, by threads tid0, tid0 + stride, ...
+  auto bg_and_deliver = [&](int64_t n, int tid0, int stride) {
+    // background-event bits for a block of four steps (one Philox call gives four words)
     if (p.has_bg && (n == n_begin || (n & 3) == 0)) {
       const uint64_t blk = (uint64_t)n >> 2;
-      for (int i = t; i < n_syn; i += T) bgm[i] = (uint8_t)bg_mask4(p.seed, syn[i].key, blk, p.bg_thresh);
+      for (int i = tid0; i < n_syn; i += stride) bgm[i] = (uint8_t)bg_mask4(p.seed, syn[i].key, blk, p.bg_thresh);
     }
-    // ---- A: delivery (Sec. 2, event-driven delivery step): one thread per synapse run, in key order
-    const int e0 = seg[s], e1 = seg[s + 1];
-    for (int e = e0 + t; e < e1; e += T) {
+    // A: delivery (Sec. 2, event-driven delivery step): one thread per synapse run, in key order
+    const int sn = (int)(n - ival * M);
+    const int e0 = seg[sn], e1 = seg[sn + 1];
+    for (int e = e0 + tid0; e < e1; e += stride) {
       const uint32_t ls = ev_syn(ev[e]);
       if (e == e0 || ev_syn(ev[e - 1]) != ls) {
         S g = sg[ls];
@@ -446,7 +447,22 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         sg[ls] = g;
       }
     }
+  };
+  // These depend only on the previous step's synapse staging. With the FP32 mechanisms (whose register budget has
+  // room for it) they run, for every step but a chunk's first, during the previous step's elimination on the upper
+  // half of the threads, which the narrow deep levels leave idle.
+  constexpr bool EARLY = std::is_same<S, float>::value;
+  if (EARLY) {
+    bg_and_deliver(n_begin, t, T);
     __syncthreads();
+  }
+
+  for (int64_t n = n_begin; n < n_end; ++n) {
+    const int s = (int)(n - ival * M);
+    if (!EARLY) {
+      bg_and_deliver(n, t, T);
+      __syncthreads();
+    }
     const uint32_t bsh = (uint32_t)(n & 3);
     // ---- S: synapses, one thread per synapse over contiguous records: conductance gs = sa g (with this step's
     // background event) and current gs (v - e) to LDS; the step's decay is applied to g ahead of the next delivery
@@ -559,6 +575,9 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     }
     __syncthreads();
     __builtin_amdgcn_s_setprio(2);
+    // the next step's background bits and delivery (FP32 mechanisms), on the upper half of the threads; the
+    // elimination's first barrier waits for them
+    if (EARLY && n + 1 < n_end && t >= T / 2) bg_and_deliver(n + 1, t - T / 2, T / 2);
     // the sweeps, with level starts read from lane registers when the group has fewer than 64 levels
     auto sweeps = [&](auto lane_bounds) {
       constexpr bool LR = decltype(lane_bounds)::value;
