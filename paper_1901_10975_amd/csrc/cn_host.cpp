@@ -118,6 +118,8 @@ struct cn_model {
   std::vector<int64_t> dev_of_syn, syn_of_dev;    // caller ExpSyn <-> device synapse
   std::vector<int64_t> icl_of_dev;                // device IClamp -> caller instance
   std::vector<int32_t> cell_of_devcell;           // device cell slot -> caller cell
+  std::vector<int64_t> tree_par;                  // parent of each caller compartment in the rooted tree (-1: root)
+  std::vector<int64_t> cell_root;                 // each caller cell's root compartment
   // per device node, kept for the dt-dependent node records
   std::vector<double> host_a, host_b, host_sa;
   std::vector<uint8_t> host_mf;
@@ -126,7 +128,7 @@ struct cn_model {
   std::vector<uint64_t> host_syn_key;
   std::vector<double> host_syn_e, host_syn_wbg;
   std::vector<int32_t> host_syn_q;
-  int32_t max_levels = 0, max_group_syn = 0, max_group_nodes = 0;
+  int32_t max_levels = 0, max_group_syn = 0, max_group_nodes = 0, max_group_cells = 0;
 
   // ---- device
   hipStream_t stream = nullptr;
@@ -304,13 +306,90 @@ void build_layout(cn_model *m) {
     const int64_t i0 = m->cell_off[c], n = m->cell_off[c + 1] - i0;
     cell_size[c] = (int32_t)n;
     max_cell = std::max<int32_t>(max_cell, (int32_t)n);
-    int32_t lv = 0;
-    for (int64_t k = 0; k < n; ++k) {
-      cell_of[i0 + k] = c;
-      depth[i0 + k] = k == 0 ? 0 : depth[i0 + m->parent[i0 + k]] + 1;
-      lv = std::max(lv, depth[i0 + k] + 1);
+    for (int64_t k = 0; k < n; ++k) cell_of[i0 + k] = c;
+  }
+  // Each cell's tree is rooted at a centre, a compartment of least eccentricity (the first in caller order on
+  // ties): the tree matrix is the same linear system whichever compartment the elimination ends at (an edge seen
+  // from its other end swaps its a and b), and a centre gives the fewest levels to sweep. The soma (compartment 0)
+  // stays the cell's threshold compartment.
+  m->tree_par.assign(N, -1);
+  m->cell_root.assign(m->n_cells, 0);
+  {
+    std::vector<int64_t> aoff(N + 1, 0), adj(2 * (size_t)std::max<int64_t>(N - m->n_cells, 0));
+    for (int64_t i = 0; i < N; ++i) {
+      const int64_t loc = i - m->cell_off[cell_of[i]];
+      if (loc > 0) {
+        aoff[i + 1]++;
+        aoff[m->cell_off[cell_of[i]] + m->parent[i] + 1]++;
+      }
     }
-    cell_levels[c] = lv;
+    for (int64_t i = 0; i < N; ++i) aoff[i + 1] += aoff[i];
+    {
+      std::vector<int64_t> fill(aoff.begin(), aoff.end() - 1);
+      for (int64_t i = 0; i < N; ++i) {
+        const int64_t loc = i - m->cell_off[cell_of[i]];
+        if (loc > 0) {
+          const int64_t pi = m->cell_off[cell_of[i]] + m->parent[i];
+          adj[fill[i]++] = pi;
+          adj[fill[pi]++] = i;
+        }
+      }
+    }
+    std::vector<int32_t> dist(N, -1);
+    std::vector<int64_t> queue;
+    queue.reserve(4096);
+    // breadth-first distances from `src` over one cell; returns the farthest compartment (first on ties); when
+    // `par` is given, records each compartment's predecessor
+    auto bfs = [&](int32_t c, int64_t src, int64_t *par) {
+      const int64_t i0 = m->cell_off[c], i1 = m->cell_off[c + 1];
+      for (int64_t i = i0; i < i1; ++i) dist[i] = -1;
+      queue.clear();
+      queue.push_back(src);
+      dist[src] = 0;
+      if (par) par[src] = -1;
+      int64_t far = src;
+      for (size_t h = 0; h < queue.size(); ++h) {
+        const int64_t u = queue[h];
+        if (dist[u] > dist[far] || (dist[u] == dist[far] && u < far)) far = u;
+        for (int64_t e = aoff[u]; e < aoff[u + 1]; ++e) {
+          const int64_t w = adj[e];
+          if (dist[w] < 0) {
+            dist[w] = dist[u] + 1;
+            if (par) par[w] = u;
+            queue.push_back(w);
+          }
+        }
+      }
+      return far;
+    };
+    std::vector<int32_t> da;
+    for (int32_t c = 0; c < m->n_cells; ++c) {
+      const int64_t i0 = m->cell_off[c], i1 = m->cell_off[c + 1];
+      int64_t root = i0;
+      if (i1 - i0 > 2) {
+        // the ends a, b of a longest path; eccentricity = max(dist to a, dist to b)
+        const int64_t a = bfs(c, i0, nullptr);
+        const int64_t b = bfs(c, a, nullptr);
+        da.assign(dist.begin() + i0, dist.begin() + i1);
+        bfs(c, b, nullptr);
+        int32_t best = -1;
+        for (int64_t i = i0; i < i1; ++i) {
+          const int32_t e = std::max(da[i - i0], dist[i]);
+          if (best < 0 || e < best) {
+            best = e;
+            root = i;
+          }
+        }
+      }
+      m->cell_root[c] = root;
+      bfs(c, root, m->tree_par.data());
+      int32_t lv = 0;
+      for (int64_t i = i0; i < i1; ++i) {
+        depth[i] = dist[i];
+        lv = std::max(lv, dist[i] + 1);
+      }
+      cell_levels[c] = lv;
+    }
   }
   const Table &syn = m->mech[CN_MECH_EXPSYN];
   for (int64_t k = 0; k < syn.n; ++k) syn_per_cell[cell_of[syn.node[k]]]++;
@@ -382,21 +461,14 @@ void build_layout(cn_model *m) {
   int32_t cell_base = 0;
   // children lists per caller compartment, ascending local index
   std::vector<int64_t> ch_off(N + 1, 0), ch_list(N, 0);
-  for (int64_t i = 0; i < N; ++i) {
-    const int32_t c = cell_of[i];
-    const int64_t loc = i - m->cell_off[c];
-    if (loc > 0) ch_off[m->cell_off[c] + m->parent[i] + 1]++;
-  }
+  for (int64_t i = 0; i < N; ++i)
+    if (m->tree_par[i] >= 0) ch_off[m->tree_par[i] + 1]++;
   for (int64_t i = 0; i < N; ++i) ch_off[i + 1] += ch_off[i];
   {
     std::vector<int64_t> fill(N, 0);
     for (int64_t i = 0; i < N; ++i) {
-      const int32_t c = cell_of[i];
-      const int64_t loc = i - m->cell_off[c];
-      if (loc > 0) {
-        const int64_t p = m->cell_off[c] + m->parent[i];
-        ch_list[ch_off[p] + fill[p]++] = i;
-      }
+      const int64_t p = m->tree_par[i];
+      if (p >= 0) ch_list[ch_off[p] + fill[p]++] = i;
     }
   }
   std::vector<int64_t> lvl_nodes, next;
@@ -412,7 +484,7 @@ void build_layout(cn_model *m) {
     int64_t pos = 0;
     lvl_nodes.clear();
     for (int32_t c : gcells[g]) {
-      lvl_nodes.push_back(m->cell_off[c]);
+      lvl_nodes.push_back(m->cell_root[c]);
       m->cell_of_devcell.push_back(c);
     }
     int32_t levels = 0;
@@ -433,6 +505,7 @@ void build_layout(cn_model *m) {
     gd.n_nodes = (int32_t)pos;
     m->max_levels = std::max(m->max_levels, levels);
     m->max_group_nodes = std::max<int32_t>(m->max_group_nodes, (int32_t)pos);
+    m->max_group_cells = std::max<int32_t>(m->max_group_cells, gd.n_cells);
     node_base += pos;
     cell_base += gd.n_cells;
   }
@@ -513,14 +586,15 @@ static void build_tables(cn_model *m) {
     const GroupDesc &gd = m->groups[grp_of_dev[dn]];
     // caller cell of i
     const int64_t c = std::upper_bound(m->cell_off.begin(), m->cell_off.end(), i) - m->cell_off.begin() - 1;
-    const int64_t loc = i - m->cell_off[c];
     sa[dn] = 100.0 / m->area[i];
-    if (loc == 0) {
+    const int64_t pi = m->tree_par[i];
+    if (pi < 0) {
       a[dn] = b[dn] = 0.0;
       par[dn] = -1;
     } else {
-      const int64_t pi = m->cell_off[c] + m->parent[i];
-      const double g = 1.0 / m->ri[i];
+      // the edge's axial resistance sits at the compartment that is the child in the caller's tree
+      const bool same = i != m->cell_off[c] && m->cell_off[c] + m->parent[i] == pi;
+      const double g = 1.0 / m->ri[same ? i : pi];
       a[dn] = -100.0 * g / m->area[pi];
       b[dn] = -100.0 * g / m->area[i];
       const int64_t pd = m->dev_of_node[pi];
@@ -686,14 +760,22 @@ static void build_tables(cn_model *m) {
   }
   // cells in device order
   {
-    std::vector<int32_t> gid(m->n_cells);
+    std::vector<int32_t> gid(m->n_cells), soma(m->n_cells);
     std::vector<double> th(m->n_cells);
-    for (int32_t c = 0; c < m->n_cells; ++c) {
-      gid[c] = m->cell_of_devcell[c];
-      th[c] = m->theta[m->cell_of_devcell[c]];
+    for (int64_t g = 0; g < m->n_groups; ++g) {
+      const GroupDesc &gd = m->groups[g];
+      for (int32_t k = 0; k < gd.n_cells; ++k) {
+        const int32_t c = gd.cell_base + k;
+        gid[c] = m->cell_of_devcell[c];
+        th[c] = m->theta[m->cell_of_devcell[c]];
+        const int64_t sd = m->dev_of_node[m->cell_off[m->cell_of_devcell[c]]] - gd.node_base;
+        if (sd < 0 || sd >= gd.n_nodes) layout_fail("soma position");
+        soma[c] = (int32_t)sd;
+      }
     }
     p.cell_gid = m->upload(gid);
     p.cell_theta = m->upload(th);
+    p.cell_soma = m->upload(soma);
   }
   // network: targets, source CSR; kicks by (group, step, id)
   {
@@ -886,6 +968,9 @@ static void prepare_dt(cn_model *m, double dt) {
   off += (m->max_levels + 1) * 4;
   p.lds_bg_off = off;
   off += std::max<int32_t>(m->max_group_syn, 1);
+  off = (off + 15) / 16 * 16;
+  p.lds_cell_off = off;  // per cell: threshold and soma potential (doubles), soma position (32-bit)
+  off += m->max_group_cells * 20;
   off = (off + 15) / 16 * 16;
   p.lds_misc_off = off;
   off += 16;

@@ -86,7 +86,7 @@ struct KParams {
   int32_t ev_cap;
   int32_t nmax;  // nodes per group (LDS rows)
   int32_t has_bg;
-  int32_t lds_ev_off, lds_seg_off, lds_lvl_off, lds_bg_off, lds_misc_off, lds_cst_off, lds_exp_off;
+  int32_t lds_ev_off, lds_seg_off, lds_lvl_off, lds_bg_off, lds_cell_off, lds_misc_off, lds_cst_off, lds_exp_off;
   const double *exp_tab;   // 2^(j/64), j = 0..63
   // node tables (device order)
   const NodeRec *nrec;
@@ -105,6 +105,7 @@ struct KParams {
   // cells (device order)
   const int32_t *cell_gid;
   const double *cell_theta;
+  const int32_t *cell_soma;  // group-local position of each cell's soma (its threshold compartment)
   // network
   const void *nc_w;        // by NetCon id, double or float
   const int32_t *nc_tgt_group, *nc_tgt_lsyn, *nc_D;

@@ -365,7 +365,12 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
   auto c_a = [&](int q) { return CL ? a_l[q] : p.nrec[nb + q].a; };
   auto c_b = [&](int q) { return CL ? b_l[q] : p.nrec[nb + q].b; };
   auto c_k = [&](int q) { return CL ? k_l[q] : p.nrec[nb + q].k; };
-  auto c_par = [&](int q) { return CL ? par_l[q] : p.nidx[nb + q].par; };
+  // the parent row packs the parent (12 bits, 4095 at a root) and the node's first synapse (20 bits)
+  auto c_par = [&](int q) {
+    if (!CL) return p.nidx[nb + q].par;
+    const int pw = par_l[q] & 0xFFF;
+    return pw == 0xFFF ? -1 : pw;
+  };
   // children: first child as a byte offset (position times 8) | count << 16
   auto c_ch = [&](int q) {
     if (CL) return ch_l[q];
@@ -385,33 +390,35 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
       a_l[q] = nr.a;
       b_l[q] = nr.b;
       k_l[q] = nr.k;
-      par_l[q] = nx.par;
+      par_l[q] = (nx.par < 0 ? 0xFFF : nx.par) | (int)((uint32_t)nx.syn0 << 12);
       ch_l[q] = ((nx.ch & 0xFFFFu) << 3) | (nx.ch & 0xFFFF0000u);
     }
   }
-  // per-slot registers for the whole chunk: channel states, parent, counts-and-flags, first synapse
+  // per-slot registers for the whole chunk: channel states, counts-and-flags
   StRec<S> rs[K];
-  int rpar[K], rsyn0[K];
   uint32_t rpk[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const int q = j * T + t;
     rs[j] = StRec<S>{};
-    rpar[j] = -1;
     rpk[j] = 0u;
-    rsyn0[j] = 0;
     if (q < N) {
       const NodeIdx nx = p.nidx[nb + q];
-      rpar[j] = nx.par;
       rpk[j] = nx.pk;
-      rsyn0[j] = nx.syn0;
       rs[j] = st[nb + q];
     }
   }
   if (!p.has_bg)
     for (int i = t; i < n_syn; i += T) bgm[i] = 0;
-  const int lv1 = lv[1];
-  const double theta0 = t < lv1 ? p.cell_theta[gd.cell_base + t] : 0.0;
+  // per cell of the group, on chip: threshold, soma potential before the step, soma position
+  const int NC = gd.n_cells;
+  double *theta_l = reinterpret_cast<double *>(lds + p.lds_cell_off);
+  double *vold_l = theta_l + NC;
+  int *soma_l = reinterpret_cast<int *>(vold_l + NC);
+  for (int c = t; c < NC; c += T) {
+    theta_l[c] = p.cell_theta[gd.cell_base + c];
+    soma_l[c] = p.cell_soma[gd.cell_base + c];
+  }
   if (t == 0) {
     P_l[NMAX] = 0.0;
     Q_l[NMAX] = 0.0;
@@ -492,7 +499,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
       od[j] = orhs[j] = odv[j] = 0.0;
       if (q < N) {
         const int64_t i = nb + q;
-        const int par = rpar[j];
+        const int par = c_par(q);
         const uint32_t pk = rpk[j];
         const double v = V_l[q];
         double rhs = 0.0, d = 0.0;
@@ -533,7 +540,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         }
         const int n_s = (int)(pk & 0xFFFFu);
         if (n_s) {
-          const int syn0 = rsyn0[j];
+          const int syn0 = (CL && staged) ? (int)((uint32_t)par_l[q] >> 12) : p.nidx[i].syn0;
           if (staged) {
             for (int c = syn0; c < syn0 + n_s; ++c) {
               rhs -= IS_l[c];
@@ -578,10 +585,9 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     // the next step's background bits and delivery (FP32 mechanisms), on the upper half of the threads; the
     // elimination's first barrier waits for them
     if (EARLY && n + 1 < n_end && t >= T / 2) bg_and_deliver(n + 1, t - T / 2, T / 2);
-    // the sweeps, with level starts read from lane registers when the group has fewer than 64 levels
-    auto sweeps = [&](auto lane_bounds) {
-      constexpr bool LR = decltype(lane_bounds)::value;
-      auto LVB = [&](int L) -> int { return LR ? __builtin_amdgcn_readlane(lvr, L) : lv[L]; };
+    // the sweeps; level starts are read from lane registers when the group has fewer than 64 levels
+    auto sweeps = [&]() {
+      auto LVB = [&](int L) -> int { return __builtin_amdgcn_readlane(lvr, L); };
       // ---- T: elimination, deepest level first, one thread per node of the level. A level's own inputs are final
       // before it starts, so each thread loads them one level ahead; after a barrier only the children's
       // contributions remain to be read.
@@ -602,22 +608,15 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         q = nq;
         cur = nxt;
       }
-      // ---- R: roots (level 0 holds the group's cells in order): solve, v update, threshold detection
+      // ---- R: roots (level 0 holds the group's cells in order): solve and v update
       for (; q < hi; q += T) {
         const TriIn x = q == t ? cur : tri_in(q);
         double d = x.d, rhs = x.r;
         gather_children(x.ch, NMAX * 8, P_l, Q_l, d, rhs);
         const double xs = rhs * rcp64(d);
-        const double vold = x.dv;
-        const double vnew = vold + xs;
+        const double vnew = x.dv + xs;
         P_l[q] = xs;
         V_l[q] = vnew;
-        const double th = q == t ? theta0 : p.cell_theta[gd.cell_base + q];
-        if (vold < th && th <= vnew) {
-          const int idx = atomicAdd(&misc[1], 1);
-          p.gsp_pack[gd.spk_base + idx] = q | ((s + 1) << 16);
-          p.gsp_frac[gd.spk_base + idx] = (th - vold) / (vnew - vold);
-        }
         if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
       }
       __syncthreads();
@@ -628,11 +627,11 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
       // done, so each thread loads and folds them one pass ahead.
       if (D > 1) {
         constexpr int BL = 3;
-        // inputs of node q in a pass whose deeper levels start at m1, m2: x = cu - cw x[cs], v = cv + x
-        auto pass_in = [&](int q, int m1, int m2, double &cu, double &cw, double &cv, int &cs) {
+        // inputs of node q in a pass whose deeper levels start at m1, m2: x = cu - cw x[cs] (v, read after the
+        // barrier in the same round trip as x[cs], gets v + x)
+        auto pass_in = [&](int q, int m1, int m2, double &cu, double &cw, int &cs) {
           cu = u_l[q];
           cw = w_l[q];
-          cv = V_l[q];
           cs = c_par(q);
           const int j = (q >= m1) + (q >= m2);
           for (int i = 0; i < j; ++i) {
@@ -644,9 +643,9 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         };
         int bm1 = LVB(min(2, D)), bm2 = LVB(min(3, D)), bend = LVB(min(1 + BL, D));
         int bq = LVB(1) + t;
-        double cu = 0.0, cw = 0.0, cv = 0.0;
+        double cu = 0.0, cw = 0.0;
         int cs = 0;
-        if (bq < bend) pass_in(bq, bm1, bm2, cu, cw, cv, cs);
+        if (bq < bend) pass_in(bq, bm1, bm2, cu, cw, cs);
         for (int L0 = 1; L0 < D; L0 += BL) {  // this pass: levels L0 .. L0 + BL - 1, nodes [bq - t, bend)
           const int L1 = L0 + BL;
           int nm1 = 0, nm2 = 0, nend = 0;
@@ -656,21 +655,21 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
             nend = LVB(min(L1 + BL, D));
           }
           const int nq = bend + t;
-          double nu = 0.0, nw = 0.0, nv = 0.0;
+          double nu = 0.0, nw = 0.0;
           int ns = 0;
-          if (nq < nend) pass_in(nq, nm1, nm2, nu, nw, nv, ns);
+          if (nq < nend) pass_in(nq, nm1, nm2, nu, nw, ns);
           if (bq < bend) {
             const double x = cu - cw * P_l[cs];
             P_l[bq] = x;
-            V_l[bq] = cv + x;
+            V_l[bq] += x;
           }
           for (int q2 = bq + T; q2 < bend; q2 += T) {  // passes wider than the group's threads
-            double u2, w2, v2;
+            double u2, w2;
             int s2;
-            pass_in(q2, bm1, bm2, u2, w2, v2, s2);
+            pass_in(q2, bm1, bm2, u2, w2, s2);
             const double x = u2 - w2 * P_l[s2];
             P_l[q2] = x;
-            V_l[q2] = v2 + x;
+            V_l[q2] += x;
           }
           __syncthreads();
           bq = nq;
@@ -679,13 +678,50 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
           bend = nend;
           cu = nu;
           cw = nw;
-          cv = nv;
           cs = ns;
         }
       }
     };
-    if (D < 64) sweeps(std::true_type{});
-    else sweeps(std::false_type{});
+    // each soma's potential before the step (the same thread reads it back after the sweeps)
+    for (int c = t; c < NC; c += T) vold_l[c] = V_l[soma_l[c]];
+    // the same sweeps without the look-ahead, for groups of 64 or more levels (level starts from LDS)
+    auto plain_sweeps = [&]() {
+      for (int L = D - 1; L >= 1; --L) {
+        for (int q = lv[L] + t; q < lv[L + 1]; q += T) tri_node(q, tri_in(q), NMAX * 8, w_l, u_l, P_l, Q_l);
+        __syncthreads();
+      }
+      for (int q = t; q < lv[1]; q += T) {
+        const TriIn x = tri_in(q);
+        double d = x.d, rhs = x.r;
+        gather_children(x.ch, NMAX * 8, P_l, Q_l, d, rhs);
+        const double xs = rhs * rcp64(d);
+        const double vnew = x.dv + xs;
+        P_l[q] = xs;
+        V_l[q] = vnew;
+        if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
+      }
+      __syncthreads();
+      for (int L = 1; L < D; ++L) {
+        for (int q = lv[L] + t; q < lv[L + 1]; q += T) {
+          const double x = u_l[q] - w_l[q] * P_l[c_par(q)];
+          P_l[q] = x;
+          V_l[q] += x;
+        }
+        __syncthreads();
+      }
+    };
+    if (D < 64) sweeps();
+    else plain_sweeps();
+    // ---- threshold detection at each cell's soma (Sec. 2): upward crossing between the step's old and new
+    // potential
+    for (int c = t; c < NC; c += T) {
+      const double vnew = V_l[soma_l[c]], vold = vold_l[c], th = theta_l[c];
+      if (vold < th && th <= vnew) {
+        const int idx = atomicAdd(&misc[1], 1);
+        p.gsp_pack[gd.spk_base + idx] = c | ((s + 1) << 16);
+        p.gsp_frac[gd.spk_base + idx] = (th - vold) / (vnew - vold);
+      }
+    }
   }
 
   // ---- epilogue: potentials and states back to global memory; the chunk's spikes (count in gsp_cnt) are recorded
