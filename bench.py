@@ -1,8 +1,8 @@
 """Benchmark: compartment-timesteps per second of the fixed-step cable engine on one MI355X.
 
-Workload: config 3 - 50,000 cells with log-uniform 50..1000 compartments (15.93M compartments), hh + km + cahi in
+Workload: cortex_50k - 50,000 cells with log-uniform 50..1000 compartments (15.93M compartments), hh + km + cahi in
 every compartment, 100 ExpSyn per cell fed by NetCons with delays U(1, 5) ms (1 ms minimum-delay interval, 40 steps
-of 0.025 ms) and 5 Hz Poisson background per synapse. Synthetic, seeded inputs (synth.config3).
+of 0.025 ms) and 5 Hz Poisson background per synapse. Synthetic, seeded inputs (synth.cortex_50k).
 
 One benchmark step = one minimum-delay interval (40 time steps: delivery, mechanisms, assembly, tree solve,
 threshold detection, and the interval's spike fan-out). Inputs are resident in HBM before the timed region.
@@ -21,10 +21,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # FP64 vector peak: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops (FMA) x 2.4 GHz
 FP64_PEAK_TFLOPS = 78.6
-# algorithmic FP64 work per compartment-step of config 3 (hh, km, cahi rates and gates, currents, assembly and the
+# algorithmic FP64 work per compartment-step of cortex_50k (hh, km, cahi rates and gates, currents, assembly and the
 # tree solve): about 500 lane operations, each exponential or divide counted as the operations it takes
 FLOPS_PER_COMP_STEP = 500.0
-PROFILE = os.path.join(ROOT, "profiles", "cn_interval_config3_traffic.json")
+PROFILE = os.path.join(ROOT, "profiles", "cn_interval_cortex50k_traffic.json")
 
 
 def bytes_per_step(m, fp32: bool) -> float:
@@ -160,8 +160,8 @@ def main():
         del a, b
 
     t0 = time.time()
-    m = synth.config3(n_cells=args.n_cells)
-    log(f"[bench] config3: {m.n_cells} cells, {m.n_comp} compartments, {m.n_syn} synapses "
+    m = synth.cortex_50k(n_cells=args.n_cells)
+    log(f"[bench] cortex_50k: {m.n_cells} cells, {m.n_comp} compartments, {m.n_syn} synapses "
         f"(generated in {time.time() - t0:.1f} s)")
     r64 = run_gpu(m, "fp64", args.steps, args.warmup, log)
     r32 = None if args.no_fp32 else run_gpu(m, "fp32_mech", args.steps, args.warmup, log)
@@ -186,7 +186,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "config3: 50000 cells, log-uniform 50-1000 compartments (%d total), hh+km+cahi, "
+        "config": {"workload": "cortex_50k: 50000 cells, log-uniform 50-1000 compartments (%d total), hh+km+cahi, "
                                "100 ExpSyn/cell, NetCon delay U(1,5) ms, Poisson 5 Hz, dt 0.025 ms; one step = one "
                                "1 ms min-delay interval (40 time steps)" % m.n_comp,
                    "n_cells": m.n_cells, "n_comp": m.n_comp, "n_syn": m.n_syn, "interval_steps": r64["M"]},

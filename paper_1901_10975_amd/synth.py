@@ -8,18 +8,18 @@ as given inputs.
 
 Units follow the cable equation of Sec. 2 (Eq. 1): mV, ms, um, um^2, MOhm, uF/cm^2, S/cm^2, nA, uS.
 
-Workload recipes (cells drawn from ``numpy.random.default_rng(10975 + config)``):
+Workload recipes (each draws its cells from ``numpy.random.default_rng`` with a fixed per-recipe seed):
 
-* config 1: 64 cells x 32 compartments, hh at the soma, pas on the dendrites, an IClamp at each soma.
-* config 2: 1,000 cells x 200 compartments, hh everywhere, 10 ExpSyn per cell each fed by one NetCon from a random
-  other cell, 5 cells kicked at step 0 (a ring-style network, the shape of the paper's Ring model, Table 1).
-* config 3: 50,000 cells with log-uniform 50..1000 compartments, hh + km + cahi everywhere, 100 ExpSyn per cell,
-  Poisson background at 5 Hz per synapse (a cortex-like shape, Table 1).
-* config 4: config 2's network, to be run with FP32 mechanism states.
-* config 5: 200,000 cells with log-uniform 100..2000 compartments, hh + pas + km + cahi everywhere, 100 ExpSyn per
-  cell, NetCon delays U(0.5, 10) ms, Poisson 5 Hz.
+* ``clamped_cells``: 64 cells x 32 compartments, hh at the soma, pas on the dendrites, an IClamp at each soma.
+* ``ring_network``: 1,000 cells x 200 compartments, hh everywhere, 10 ExpSyn per cell each fed by one NetCon from
+  a random other cell, 5 cells kicked at step 0 (a ring-style network, the shape of the paper's Ring model,
+  Table 1); 200 ms by default, 100 ms where it exercises the FP32-mechanism path.
+* ``cortex_50k``: 50,000 cells with log-uniform 50..1000 compartments, hh + km + cahi everywhere, 100 ExpSyn per
+  cell, Poisson background at 5 Hz per synapse (a cortex-like shape, Table 1).
+* ``cortex_200k``: 200,000 cells with log-uniform 100..2000 compartments, hh + pas + km + cahi everywhere, 100
+  ExpSyn per cell, NetCon delays U(0.5, 10) ms, Poisson 5 Hz.
 
-Every config takes ``n_cells`` to build a smaller network with the same recipe (tests use this).
+Every recipe takes ``n_cells`` to build a smaller network the same way (tests use this).
 """
 from __future__ import annotations
 
@@ -178,7 +178,7 @@ def _base(off, parent, area, ri, mechs, **kw) -> Model:
     return Model(**d)
 
 
-def config1(n_cells: int = 64, seed: Optional[int] = None) -> Model:
+def clamped_cells(n_cells: int = 64, seed: Optional[int] = None) -> Model:
     rng = np.random.default_rng(10975 + 1 if seed is None else seed)
     sizes = np.full(n_cells, 32, dtype=np.int64)
     off, parent, area, ri = _random_trees(rng, sizes)
@@ -191,7 +191,7 @@ def config1(n_cells: int = 64, seed: Optional[int] = None) -> Model:
         "pas": MechTable(node=dend, params=dict(PAS_PARAMS)),
         "iclamp": MechTable(node=soma.copy(), params={"del": 1.0, "dur": 100.0, "amp": amp}),
     }
-    return _base(off, parent, area, ri, mechs, tstop=100.0, name="config1")
+    return _base(off, parent, area, ri, mechs, tstop=100.0, name="clamped_cells")
 
 
 def _ring(n_cells, n_comp, seed, tstop, name) -> Model:
@@ -207,13 +207,9 @@ def _ring(n_cells, n_comp, seed, tstop, name) -> Model:
                  kick_weight=np.full(nk, 0.1), tstop=tstop, name=name)
 
 
-def config2(n_cells: int = 1000, n_comp: int = 200, seed: Optional[int] = None) -> Model:
-    return _ring(n_cells, n_comp, 10975 + 2 if seed is None else seed, 200.0, "config2")
-
-
-def config4(n_cells: int = 1000, n_comp: int = 200, seed: Optional[int] = None) -> Model:
-    """Config 2's network (same seed), run for 100 ms with FP32 mechanism states."""
-    return _ring(n_cells, n_comp, 10975 + 2 if seed is None else seed, 100.0, "config4")
+def ring_network(n_cells: int = 1000, n_comp: int = 200, seed: Optional[int] = None,
+                 tstop: float = 200.0) -> Model:
+    return _ring(n_cells, n_comp, 10975 + 2 if seed is None else seed, tstop, "ring_network")
 
 
 def _cortex(n_cells, lo, hi, mech_names, d_lo, d_hi, seed, tstop, name) -> Model:
@@ -236,21 +232,18 @@ def _cortex(n_cells, lo, hi, mech_names, d_lo, d_hi, seed, tstop, name) -> Model
                  poisson_rate_hz=5.0, poisson_weight=w.copy(), seed=int(seed), tstop=tstop, name=name)
 
 
-def config3(n_cells: int = 50000, seed: Optional[int] = None) -> Model:
+def cortex_50k(n_cells: int = 50000, seed: Optional[int] = None) -> Model:
     return _cortex(n_cells, 50, 1000, ("hh", "km", "cahi"), 1.0, 5.0, 10975 + 3 if seed is None else seed,
-                   100.0, "config3")
+                   100.0, "cortex_50k")
 
 
-def config5(n_cells: int = 200000, seed: Optional[int] = None) -> Model:
+def cortex_200k(n_cells: int = 200000, seed: Optional[int] = None) -> Model:
     return _cortex(n_cells, 100, 2000, ("hh", "pas", "km", "cahi"), 0.5, 10.0,
-                   10975 + 5 if seed is None else seed, 50.0, "config5")
+                   10975 + 5 if seed is None else seed, 50.0, "cortex_200k")
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
-
-
-def make_config(cfg: int, **kw) -> Model:
-    return CONFIGS[cfg](**kw)
+WORKLOADS = {"clamped_cells": clamped_cells, "ring_network": ring_network, "cortex_50k": cortex_50k,
+             "cortex_200k": cortex_200k}
 
 
 def subset_cells(m: Model, cells: np.ndarray) -> Model:

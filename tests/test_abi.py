@@ -96,15 +96,15 @@ def test_null_arguments_are_errors_not_crashes():
     L.cn_model_destroy(None)
 
 
-@pytest.mark.parametrize("name", ["config1", "config2_small", "config3_small", "config5_small", "edge"])
+@pytest.mark.parametrize("name", ["clamped_cells", "ring_small", "cortex_50k_small", "cortex_200k_small", "edge"])
 def test_host_layout_checks_pass(name):
     """the device layout (cell groups, level order, instance ranges, event targets) satisfies every invariant the
     interval kernel indexes by; built and checked on the host only"""
     from tests.test_gpu_parity import _edge_model
-    model = {"config1": lambda: synth.config1(),
-             "config2_small": lambda: synth.config2(n_cells=100, n_comp=200),
-             "config3_small": lambda: synth.config3(n_cells=3000),
-             "config5_small": lambda: synth.config5(n_cells=300),
+    model = {"clamped_cells": lambda: synth.clamped_cells(),
+             "ring_small": lambda: synth.ring_network(n_cells=100, n_comp=200),
+             "cortex_50k_small": lambda: synth.cortex_50k(n_cells=3000),
+             "cortex_200k_small": lambda: synth.cortex_200k(n_cells=300),
              "edge": _edge_model}[name]()
     e = cn.Engine(model, use_torch=False, validate_only=True)
     info = e.info()

@@ -50,11 +50,11 @@ def _spike_steps_within_one(orc, eng, cells):
     return n, worst
 
 
-def test_config4_fp32_mech_100ms():
-    """config 4: config 2's network in the FP32-mechanism path, 100 ms, errors on cells 0-499"""
-    m = synth.config4()
+def test_ring_network_fp32_mech_100ms():
+    """the ring network in the FP32-mechanism path, 100 ms, errors on cells 0-499"""
+    m = synth.ring_network(tstop=100.0)
     cells = np.arange(500)
-    say("config4 fp32_mech 100 ms")
+    say("ring_network fp32_mech 100 ms")
     orc, eng, linf, med = _run(m, list(range(400, 4001, 400)), cells=cells)
     n, worst = _spike_steps_within_one(orc, eng, cells)
     say(f"  cells 0-499: {n} spikes, max |step difference| {worst}, voltage Linf {linf:.3g} mV, median {med:.3g} mV")
@@ -64,10 +64,10 @@ def test_config4_fp32_mech_100ms():
 
 
 @pytest.mark.parametrize("threads", [0, 512])
-def test_config3_recipe_fp32_mech(threads):
-    m = synth.config3(n_cells=400)
+def test_cortex_50k_recipe_fp32_mech(threads):
+    m = synth.cortex_50k(n_cells=400)
     cells = np.arange(m.n_cells)
-    say(f"config3 recipe fp32_mech, 400 cells, 20 ms, group_threads {threads}")
+    say(f"cortex_50k recipe fp32_mech, 400 cells, 20 ms, group_threads {threads}")
     orc, eng, linf, med = _run(m, list(range(40, 801, 40)), group_threads=threads)
     n, worst = _spike_steps_within_one(orc, eng, cells)
     say(f"  {n} spikes, max |step difference| {worst}, voltage Linf {linf:.3g} mV, median {med:.3g} mV")
@@ -75,10 +75,10 @@ def test_config3_recipe_fp32_mech(threads):
     assert med < 1e-3
 
 
-def test_config5_recipe_fp32_mech():
-    m = synth.config5(n_cells=60)
+def test_cortex_200k_recipe_fp32_mech():
+    m = synth.cortex_200k(n_cells=60)
     cells = np.arange(m.n_cells)
-    say("config5 recipe fp32_mech, 60 cells, 10 ms")
+    say("cortex_200k recipe fp32_mech, 60 cells, 10 ms")
     orc, eng, linf, med = _run(m, list(range(20, 401, 20)))
     n, worst = _spike_steps_within_one(orc, eng, cells)
     say(f"  {n} spikes, max |step difference| {worst}, voltage Linf {linf:.3g} mV, median {med:.3g} mV")

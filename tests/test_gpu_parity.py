@@ -6,7 +6,7 @@ FP64 path, at every checkpoint:
     dev(t) <= max(1e-10, 10 * s(t)), where s(t) is the largest value of the same metric between the oracle and an
     ensemble of rounding-level variants of itself: v_init moved one ulp up and down, every NetCon weight moved one
     ulp, and the oracle built with fused multiply-add contraction. s(t) is the problem's own sensitivity to
-    rounding: spike upstrokes and near-threshold inputs amplify rounding differences (on config 2 a one-ulp change
+    rounding: spike upstrokes and near-threshold inputs amplify rounding differences (on the ring network a one-ulp change
     of the weights alone grows to 4e-9 by 40 ms), so two correctly rounded implementations that round differently
     cannot stay within 1e-10 of each other on an active network. Where the dynamics do not amplify, s(t) stays
     below 1e-11 and the bar is 1e-10.
@@ -97,28 +97,28 @@ def assert_spikes_equal(orc, eng, min_count=1):
     np.testing.assert_allclose(tg, to, rtol=0, atol=max(1e-9, KSENS * getattr(orc, "sens_t", 0.0)))
 
 
-def test_config1_full():
-    m = synth.config1()
-    say("config1 64x32 100 ms")
+def test_clamped_cells_full():
+    m = synth.clamped_cells()
+    say("clamped_cells 64x32 100 ms")
     orc, eng, worst = lockstep(m, range(40, 4001, 40), sensitivity=False)  # plain 1e-10 bar throughout
     assert worst <= 1.0, worst
     assert_spikes_equal(orc, eng, min_count=10)
 
 
-def test_config2_ring_100ms():
-    m = synth.config2()
-    say("config2 1000x200 100 ms")
+def test_ring_network_100ms():
+    m = synth.ring_network()
+    say("ring_network 1000x200 100 ms")
     orc, eng, worst = lockstep(m, range(200, 4001, 200))
     assert worst <= 1.0, worst
     assert_spikes_equal(orc, eng, min_count=100)
 
 
 @pytest.mark.parametrize("threads", [0, 512])
-def test_config3_recipe_400_cells(threads):
-    """config 3's recipe on 400 cells; threads=512 is the launch shape the full-size workload takes (512 threads,
+def test_cortex_50k_recipe_400_cells(threads):
+    """the cortex_50k recipe on 400 cells; threads=512 is the launch shape the full-size workload takes (512 threads,
     two register slots, 1024-compartment groups)"""
-    m = synth.config3(n_cells=400)
-    say(f"config3 recipe, 400 cells, 20 ms, group_threads {threads}")
+    m = synth.cortex_50k(n_cells=400)
+    say(f"cortex_50k recipe, 400 cells, 20 ms, group_threads {threads}")
     orc, eng, worst = lockstep(m, range(40, 801, 40), group_threads=threads)
     assert worst <= 1.0, worst
     assert_spikes_equal(orc, eng, min_count=50)
@@ -128,9 +128,9 @@ def test_config3_recipe_400_cells(threads):
         assert info["group_threads"] == 512 and info["group_slots"] == 2
 
 
-def test_config5_recipe_60_cells():
-    m = synth.config5(n_cells=60)
-    say("config5 recipe, 60 cells, 10 ms")
+def test_cortex_200k_recipe_60_cells():
+    m = synth.cortex_200k(n_cells=60)
+    say("cortex_200k recipe, 60 cells, 10 ms")
     orc, eng, worst = lockstep(m, range(20, 401, 20))
     assert worst <= 1.0, worst
     assert_spikes_equal(orc, eng, min_count=1)
@@ -141,7 +141,7 @@ def test_config5_recipe_60_cells():
 def test_per_compartment_parameters(threads):
     """density-mechanism parameters that differ between compartments (the per-node parameter table path), over
     25 ms of an active network (weights x4): beyond that, rounding differences grow chaotically on this network"""
-    m = synth.config2(n_cells=120, n_comp=150, seed=31)
+    m = synth.ring_network(n_cells=120, n_comp=150, seed=31)
     rng = np.random.default_rng(31)
     hh = m.mechs["hh"]
     k = m.n_comp if hh.node is None else hh.node.size
@@ -157,7 +157,7 @@ def test_per_compartment_parameters(threads):
 
 
 def test_irregular_run_lengths_and_graph_off():
-    m = synth.config2(n_cells=80, n_comp=60, seed=21)
+    m = synth.ring_network(n_cells=80, n_comp=60, seed=21)
     m.nc_weight = m.nc_weight * 10
     steps = np.cumsum([1, 6, 13, 40, 41, 2, 80, 39, 120, 7, 300])
     say("irregular chunks")
@@ -167,7 +167,7 @@ def test_irregular_run_lengths_and_graph_off():
 
 
 def test_graph_and_direct_launches_bitwise_equal():
-    m = synth.config3(n_cells=120, seed=5)
+    m = synth.cortex_50k(n_cells=120, seed=5)
     say("graph vs direct")
     a = _engine(m, use_graph=True)
     b = _engine(m, use_graph=False)
@@ -179,7 +179,7 @@ def test_graph_and_direct_launches_bitwise_equal():
 
 
 def test_determinism_two_runs():
-    m = synth.config3(n_cells=150, seed=6)
+    m = synth.cortex_50k(n_cells=150, seed=6)
     say("determinism")
     runs = []
     for _ in range(2):
@@ -226,7 +226,7 @@ def test_edge_shapes_kicks_and_clamps():
 
 
 def test_states_parity():
-    m = synth.config3(n_cells=50, seed=8)
+    m = synth.cortex_50k(n_cells=50, seed=8)
     say("states")
     orc = O.OracleSim(m, n_threads=THREADS)
     eng = _engine(m)
@@ -244,7 +244,7 @@ def test_states_parity():
 
 def test_event_capacity_overflow_is_reported():
     from paper_1901_10975_amd import cn
-    m = synth.config2(n_cells=40, n_comp=20, seed=3)
+    m = synth.ring_network(n_cells=40, n_comp=20, seed=3)
     m.nc_weight = m.nc_weight * 20
     m.kick_step = np.zeros(40, np.int64)
     m.kick_syn = np.arange(40, dtype=np.int64) * 10
@@ -261,7 +261,7 @@ def test_event_capacity_overflow_is_reported():
 
 def test_state_errors():
     from paper_1901_10975_amd import cn
-    m = synth.config1(n_cells=4)
+    m = synth.clamped_cells(n_cells=4)
     eng = _engine(m)
     eng.run(1.0)
     from paper_1901_10975_amd.cn import lib
@@ -270,11 +270,11 @@ def test_state_errors():
     eng.run(1.0)  # same time: no-op
 
 
-def test_full_size_config3_first_interval_sampled():
-    """config 3 at full size in the benchmark's launch configuration: within the first interval no NetCon event
+def test_full_size_cortex_50k_first_interval_sampled():
+    """cortex_50k at full size in the benchmark's launch configuration: within the first interval no NetCon event
     can arrive, so each sampled cell evolves alone and the oracle can compute it on its own."""
-    m = synth.config3()
-    say("config3 full size, first interval, 300 sampled cells")
+    m = synth.cortex_50k()
+    say("cortex_50k full size, first interval, 300 sampled cells")
     eng = _engine(m)
     M = 40
     eng.run_to_step(M)
@@ -294,11 +294,11 @@ def test_full_size_config3_first_interval_sampled():
     assert np.all(np.isfinite(v))
 
 
-def test_full_size_config5_first_interval_sampled():
-    """config 5 at full size (200,000 cells, about 127M compartments, 20-step interval, 512-thread groups of up to
+def test_full_size_cortex_200k_first_interval_sampled():
+    """cortex_200k at full size (200,000 cells, about 127M compartments, 20-step interval, 512-thread groups of up to
     2048 compartments): within the first interval each sampled cell evolves alone, so the oracle computes it alone"""
-    m = synth.config5()
-    say(f"config5 full size: {m.n_cells} cells, {m.n_comp} compartments; first interval, 100 sampled cells")
+    m = synth.cortex_200k()
+    say(f"cortex_200k full size: {m.n_cells} cells, {m.n_comp} compartments; first interval, 100 sampled cells")
     eng = _engine(m)
     eng.run_to_step(20)
     assert eng.info()["interval_steps"] == 20

@@ -379,7 +379,7 @@ def test_kick_arrives_at_step_zero():
 
 
 def _small_ring(n_cells=60, n_comp=30, seed=11):
-    m = synth.config2(n_cells=n_cells, n_comp=n_comp, seed=seed)
+    m = synth.ring_network(n_cells=n_cells, n_comp=n_comp, seed=seed)
     m.nc_weight = m.nc_weight * 10.0  # strong enough for activity to propagate in a small ring
     return m
 
@@ -406,7 +406,7 @@ def test_batching_rejects_interval_longer_than_min_delay():
 
 
 def test_determinism_and_threads():
-    m = synth.config3(n_cells=40)
+    m = synth.cortex_50k(n_cells=40)
     runs = []
     for th in (1, 1, 4):
         s = O.OracleSim(m, n_threads=th)
