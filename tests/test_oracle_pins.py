@@ -4,6 +4,7 @@ Each test checks the oracle against something other than itself: a library solve
 every tree shape, the closed form of the discrete scheme, an invariant of the equations, an independent integrator
 of the continuous model, or values printed in the literature.
 """
+import dataclasses
 import itertools
 
 import numpy as np
@@ -503,3 +504,63 @@ def test_philox_avalanche():
         o2 = O.philox(c2, k)
         flips.append(sum(bin(a ^ b).count("1") for a, b in zip(o1, o2)))
     assert 60 < np.mean(flips) < 68
+
+
+def _partitioned_run(m, parts, tstop, max_passes=80):
+    """Run the cells of each partition in a model of their own, as one GPU of a sharded run would. A spike of a
+    cell outside the partition reaches the partition's synapses the way the exchange at interval ends delivers it:
+    as an event at step k + D with the NetCon's weight, here a kick. The partitions are rerun with the spikes of the
+    previous pass until the spike lists no longer change; since every delay spans at least one interval, the run
+    whose remote spikes all come from earlier intervals is that fixed point."""
+    syn_node = m.mechs["expsyn"].node
+    syn_cell = np.searchsorted(m.cell_offset, syn_node, side="right") - 1
+    D = np.floor(m.nc_delay / m.dt + 0.5).astype(np.int64)
+    n_steps = int(round(tstop / m.dt))
+    prev = None
+    for passes in range(1, max_passes + 1):
+        spikes, v = [], np.empty(m.n_comp)
+        for cells in parts:
+            inside = np.zeros(m.n_cells, bool)
+            inside[cells] = True
+            local_syn = np.full(syn_node.shape[0], -1, np.int64)
+            keep = np.nonzero(inside[syn_cell])[0]
+            local_syn[keep] = np.arange(keep.shape[0])
+            sub = synth.subset_cells(m, cells)
+            ks, kn, kw = [sub.kick_step], [sub.kick_syn], [sub.kick_weight]
+            if prev is not None:
+                remote = (~inside[m.nc_src]) & inside[syn_cell[m.nc_syn]]
+                for g, k in prev:
+                    sel = np.nonzero(remote & (m.nc_src == g))[0]
+                    ks.append(k + D[sel]); kn.append(local_syn[m.nc_syn[sel]]); kw.append(m.nc_weight[sel])
+            sub = dataclasses.replace(sub, kick_step=np.concatenate(ks).astype(np.int64),
+                                      kick_syn=np.concatenate(kn).astype(np.int64), kick_weight=np.concatenate(kw))
+            sim = O.OracleSim(sub)
+            sim.run_to_step(n_steps)
+            gid, step, t = sim.spikes()
+            spikes += [(int(cells[g]), int(k), float(x)) for g, k, x in zip(gid, step, t)]
+            nodes = np.concatenate([np.arange(m.cell_offset[c], m.cell_offset[c + 1]) for c in cells])
+            v[nodes] = sim.v()
+        spikes.sort(key=lambda s: (s[1], s[0]))
+        if prev is not None and [(g, k) for g, k, _ in spikes] == prev:
+            return spikes, v, passes
+        prev = [(g, k) for g, k, _ in spikes]
+    raise AssertionError("partitioned run did not settle")
+
+
+def test_k_partition_equals_unpartitioned():
+    """Sharding across devices (one spike exchange per minimum-delay interval, Sec. 2): cells split into K
+    partitions that see each other's spikes only through that exchange give, bitwise, the voltages and spikes of
+    the single run. Each ring synapse is fed by exactly one NetCon, so a remote event delivered as a kick is the
+    same addition at the same step."""
+    m = _small_ring(n_cells=40, n_comp=20, seed=5)
+    a = O.OracleSim(m)
+    a.run(30.0)
+    g, k, t = a.spikes()
+    ref = sorted(zip(k.tolist(), g.tolist(), t.tolist()))
+    assert len(ref) > 10
+    for K in (2, 3):
+        parts = [np.arange(j, m.n_cells, K) for j in range(K)]
+        spikes, v, passes = _partitioned_run(m, parts, 30.0)
+        assert passes >= 3  # remote spikes changed the partitions' runs
+        assert sorted((s[1], s[0], s[2]) for s in spikes) == ref
+        assert np.array_equal(v, a.v())
