@@ -25,6 +25,7 @@ FP64_PEAK_TFLOPS = 78.6
 # tree solve): about 500 lane operations, each exponential or divide counted as the operations it takes
 FLOPS_PER_COMP_STEP = 500.0
 PROFILE = os.path.join(ROOT, "profiles", "cn_interval_cortex50k_traffic.json")
+VALU_PROFILE = os.path.join(ROOT, "profiles", "cn_interval_cortex50k_valu.json")
 
 
 def bytes_per_step(m, fp32: bool) -> float:
@@ -62,6 +63,20 @@ def profiled_traffic(precision: str):
         return None
     k = rec.get("kernels", {}).get(precision)
     return None if k is None else float(k["traffic_bytes"])
+
+
+def profiled_valu(precision: str):
+    """VALU busy fraction and measured FP64 TFLOP/s of the interval kernel from the committed counter passes, or
+    None when the kernel sources changed since they were taken"""
+    try:
+        with open(VALU_PROFILE) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != kernel_sources_sha256():
+        return None
+    k = rec.get("kernels", {}).get(precision)
+    return None if k is None else {"valu_busy": k["valu_busy"], "measured_fp64_tflops": k["fp64_tflops"]}
 
 
 def run_gpu(m, precision, steps, warmup, log):
@@ -199,7 +214,8 @@ def main():
                      "kernel_ms": r64["kernel_ms"], "flops_per_launch": flops_launch,
                      "measured_hbm_GBs": None if traffic is None else traffic / kern_s / 1e9,
                      "effective_hbm_GBs": eff_gbs, "effective_hbm_frac": eff_gbs / HBM_PEAK_GBS,
-                     "per_step_method_bytes_per_launch": per_launch},
+                     "per_step_method_bytes_per_launch": per_launch,
+                     "counters": profiled_valu("fp64")},
     }
     if r32 is not None:
         bps32 = bytes_per_step(m, True)
@@ -207,7 +223,7 @@ def main():
                             "kernel_ms": r32["kernel_ms"],
                             "speedup_vs_fp64": r32["value"] / r64["value"],
                             "effective_GBs": bps32 * r32["M"] / (r32["kernel_ms"] * 1e-3) / 1e9,
-                            "traffic": profiled_traffic("fp32_mech")}
+                            "traffic": profiled_traffic("fp32_mech"), "counters": profiled_valu("fp32_mech")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, log)
     print(json.dumps(out), flush=True)
