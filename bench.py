@@ -111,13 +111,37 @@ def run_gpu(m, precision, steps, warmup, log):
     return res
 
 
-def cpu_baseline(m, log, budget_s=12.0):
+def _oracle_rate(sub, threads, budget_s):
+    """compartment-steps/s of the oracle on `sub`, advanced interval by interval until the time budget is used"""
+    from oracle import oracle as O
+
+    orc = O.OracleSim(sub, n_threads=threads)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        n += 40
+        orc.run_to_step(n)
+    el = time.perf_counter() - t0
+    return sub.n_comp * n / el, n, el
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(m, log, budget_s=12.0, budget_1_s=8.0):
     """The oracle, as it stands, on the host cores over a bounded sample of the same workload: a random 5% of the
     cells (with their synapses, background streams and the NetCons among them), advanced interval by interval until
-    the time budget is used."""
+    the time budget is used; and on one core over a random 1% of the cells."""
     import numpy as np
 
-    from oracle import oracle as O
     from paper_1901_10975_amd import synth
 
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -125,19 +149,20 @@ def cpu_baseline(m, log, budget_s=12.0):
     rng = np.random.default_rng(0)
     cells = np.sort(rng.choice(m.n_cells, max(1, m.n_cells // 20), replace=False))
     sub = synth.subset_cells(m, cells)
-    orc = O.OracleSim(sub, n_threads=cores)
-    n = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        n += 40
-        orc.run_to_step(n)
-    el = time.perf_counter() - t0
-    val = sub.n_comp * n / el
+    val, n, el = _oracle_rate(sub, cores, budget_s)
     log(f"[bench] oracle: {sub.n_cells} cells / {sub.n_comp} compartments x {n} steps in {el:.1f} s on {cores} "
         f"threads -> {val:.3e} comp-steps/s")
+    cells1 = np.sort(rng.choice(m.n_cells, max(1, m.n_cells // 100), replace=False))
+    sub1 = synth.subset_cells(m, cells1)
+    val1, n1, el1 = _oracle_rate(sub1, 1, budget_1_s)
+    log(f"[bench] oracle: {sub1.n_cells} cells / {sub1.n_comp} compartments x {n1} steps in {el1:.1f} s on 1 "
+        f"thread -> {val1:.3e} comp-steps/s")
     return {"value": val, "unit": "compartment-timesteps/s", "cores": cores, "kind": "oracle",
             "sample": f"{sub.n_cells} random cells of the workload ({sub.n_comp} compartments, their synapses, "
-                      f"background streams and internal NetCons), {n} steps of 0.025 ms, FP64, {cores} threads"}
+                      f"background streams and internal NetCons), {n} steps of 0.025 ms, FP64, {cores} threads",
+            "cpu_model": _cpu_model(),
+            "single_core": {"value": val1, "cores": 1,
+                            "sample": f"{sub1.n_cells} random cells ({sub1.n_comp} compartments), {n1} steps, FP64"}}
 
 
 def main():
@@ -226,6 +251,7 @@ def main():
                             "traffic": profiled_traffic("fp32_mech"), "counters": profiled_valu("fp32_mech")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, log)
+        out["cpu_baseline"]["gpu_over_oracle"] = r64["value"] / out["cpu_baseline"]["value"]
     print(json.dumps(out), flush=True)
 
 
