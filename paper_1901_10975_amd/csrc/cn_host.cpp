@@ -672,6 +672,11 @@ static void build_tables(cn_model *m) {
       p.prm_s[c] = tb.present ? tb.p[cols[c][1]].s : 0.0;
       if (tb.present && !tb.p[cols[c][1]].uniform) any = true;
     }
+    // the uniform kernels also need one mechanism set on every compartment; otherwise the parameters go to the
+    // table as well
+    const bool same_mechs = N == 0 || std::all_of(mf.begin(), mf.end(), [&](uint8_t x) { return x == mf[0]; });
+    p.mf_uni = N ? mf[0] : 0;
+    if (!same_mechs) any = true;
     p.prm = nullptr;
     if (any) {
       std::vector<double> t(N_PRM * (size_t)N, 0.0);
@@ -912,6 +917,7 @@ static void prepare_dt(cn_model *m, double dt) {
   p.nc_D = m->upload(D);
   // background stream threshold: event iff word < floor(p 2^32), p = rate dt 1e-3
   p.has_bg = m->rate > 0.0 ? 1 : 0;
+  p.has_icl = m->mech[CN_MECH_ICLAMP].present && m->mech[CN_MECH_ICLAMP].n > 0 ? 1 : 0;
   {
     const double pr = m->rate * dt * 1e-3;
     const double t = std::floor(pr * 4294967296.0);

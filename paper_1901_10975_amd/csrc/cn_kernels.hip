@@ -68,10 +68,9 @@ template <>
 struct Math<float> {
   static __device__ __forceinline__ float ex(float x, const lds_table *) { return __expf(x); }
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-  // 1 - exp(-z) without the cancellation of the subtraction at small z (four-term series below 0.03)
-  static __device__ __forceinline__ float omx(float z, const lds_table *) {
-    return z < 0.03f ? z * (1.0f - z * 0.5f * (1.0f - z * (1.0f / 3.0f) * (1.0f - 0.25f * z))) : 1.0f - __expf(-z);
-  }
+  // 1 - exp(-z). At small z the subtraction cancels, but the gate update multiplies it by (x_inf - x): its absolute
+  // error stays below an ulp of the state, the resolution FP32 states have anyway.
+  static __device__ __forceinline__ float omx(float z, const lds_table *) { return 1.0f - __expf(-z); }
 };
 
 __device__ __forceinline__ double rcp64(double x) { return Math<double>::rcp(x); }
@@ -235,7 +234,8 @@ constexpr int lds_row_bytes(int nmax) { return const_in_lds(nmax) ? 8 * nmax + 6
 // waves per SIMD the register budget is sized for: more register slots per thread keep more compartments on chip
 constexpr int waves_for_slots(int K) { return K <= 1 ? 4 : (K == 2 ? 3 : (K == 4 ? 2 : 1)); }
 
-// UNI: every density-mechanism parameter is uniform (read from the LDS constants, not the per-node table)
+// UNI: every compartment carries the same density mechanisms (flags in mf_uni) and every parameter is uniform
+// (read from the LDS constants, not the per-node table)
 template <int T, int K, typename S, bool UNI>
 __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -503,7 +503,8 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         const uint32_t pk = rpk[j];
         const double v = V_l[q];
         double rhs = 0.0, d = 0.0;
-        const uint32_t mf = pk >> 24;
+        // with one mechanism set on every compartment the flags are a kernel argument: uniform branches
+        const uint32_t mf = UNI ? p.mf_uni : pk >> 24;
         StRec<S> &sr = rs[j];
         if (pend) {
           if (mf & MF_HH) hh_advance<S>(v, q10dt, sr.m, sr.h, sr.n, etab3);
@@ -532,7 +533,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
           rhs -= g * (v - 120.0);
           d += g;
         }
-        const int n_icl = (int)((pk >> 16) & 0xFFu);
+        const int n_icl = (!UNI || p.has_icl) ? (int)((pk >> 16) & 0xFFu) : 0;
         if (n_icl) {
           const IclRec *ic = p.icl + gd.icl_base + p.nd_icl0[i];
           for (int c = 0; c < n_icl; ++c)
