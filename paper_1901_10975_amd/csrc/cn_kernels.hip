@@ -540,14 +540,23 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
             if (ic[c].on <= n && n < ic[c].off) rhs += ic[c].cur;
         }
         const int n_s = (int)(pk & 0xFFFFu);
-        if (n_s) {
-          const int syn0 = (CL && staged) ? (int)((uint32_t)par_l[q] >> 12) : p.nidx[i].syn0;
+        {
           if (staged) {
-            for (int c = syn0; c < syn0 + n_s; ++c) {
+            const int syn0 = CL ? (int)((uint32_t)par_l[q] >> 12) : p.nidx[i].syn0;
+            // the first two synapses unconditionally, an absent one from the rows' zero entry (index 2 NMAX + 1
+            // of the staged span is the P and Q rows' zero entry, which staging leaves alone): adding zero leaves
+            // the sums exact, in the same order
+            const int z = 2 * NMAX + 1, c0 = n_s > 0 ? syn0 : z, c1 = n_s > 1 ? syn0 + 1 : z;
+            rhs -= IS_l[c0];
+            d += GS_l[c0];
+            rhs -= IS_l[c1];
+            d += GS_l[c1];
+            for (int c = syn0 + 2; c < syn0 + n_s; ++c) {
               rhs -= IS_l[c];
               d += GS_l[c];
             }
-          } else {  // groups with more synapses than a row holds: the same terms, computed here
+          } else if (n_s) {  // groups with more synapses than a row holds: the same terms, computed here
+            const int syn0 = p.nidx[i].syn0;
             for (int ls = syn0; ls < syn0 + n_s; ++ls) {
               const SynRec<S> sy = syn[ls];
               S g = sg[ls];
