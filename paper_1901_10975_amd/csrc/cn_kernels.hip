@@ -464,12 +464,33 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     __syncthreads();
   }
 
+  // ---- threshold detection at each cell's soma (Sec. 2): an upward crossing between the potential before and
+  // after a step. The soma potential a step produces stays in V_l until the next step's substitution, so the test
+  // of step n runs at the top of step n + 1 (for a chunk's last step, after the loop), on the highest threads, which
+  // the synapse staging leaves idle in most groups; the potential is then kept as the next step's old one. `sn` is
+  // the step inside the interval whose potentials V_l holds.
+  auto detect = [&](int sn, bool test) {
+    for (int c = T - 1 - t; c < NC; c += T) {
+      const double vnew = V_l[soma_l[c]];
+      if (test) {
+        const double vold = vold_l[c], th = theta_l[c];
+        if (vold < th && th <= vnew) {
+          const int idx = atomicAdd(&misc[1], 1);
+          p.gsp_pack[gd.spk_base + idx] = c | (sn << 16);
+          p.gsp_frac[gd.spk_base + idx] = (th - vold) / (vnew - vold);
+        }
+      }
+      vold_l[c] = vnew;
+    }
+  };
+
   for (int64_t n = n_begin; n < n_end; ++n) {
     const int s = (int)(n - ival * M);
     if (!EARLY) {
       bg_and_deliver(n, t, T);
       __syncthreads();
     }
+    detect(s, n > n_begin);
     const uint32_t bsh = (uint32_t)(n & 3);
     // ---- S: synapses, one thread per synapse over contiguous records: conductance gs = sa g (with this step's
     // background event) and current gs (v - e) to LDS; the step's decay is applied to g ahead of the next delivery
@@ -692,8 +713,6 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         }
       }
     };
-    // each soma's potential before the step (the same thread reads it back after the sweeps)
-    for (int c = t; c < NC; c += T) vold_l[c] = V_l[soma_l[c]];
     // the same sweeps without the look-ahead, for groups of 64 or more levels (level starts from LDS)
     auto plain_sweeps = [&]() {
       for (int L = D - 1; L >= 1; --L) {
@@ -722,17 +741,8 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     };
     if (D < 64) sweeps();
     else plain_sweeps();
-    // ---- threshold detection at each cell's soma (Sec. 2): upward crossing between the step's old and new
-    // potential
-    for (int c = t; c < NC; c += T) {
-      const double vnew = V_l[soma_l[c]], vold = vold_l[c], th = theta_l[c];
-      if (vold < th && th <= vnew) {
-        const int idx = atomicAdd(&misc[1], 1);
-        p.gsp_pack[gd.spk_base + idx] = c | ((s + 1) << 16);
-        p.gsp_frac[gd.spk_base + idx] = (th - vold) / (vnew - vold);
-      }
-    }
   }
+  if (n_end > n_begin) detect((int)(n_end - ival * M), true);
 
   // ---- epilogue: potentials and states back to global memory; the chunk's spikes (count in gsp_cnt) are recorded
   // and fanned out by cn_fanout
@@ -742,6 +752,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     const int q = j * T + t;
     if (q < N) st[nb + q] = rs[j];
   }
+  __syncthreads();  // every detection's count is in
   if (t == 0) {
     p.gsp_cnt[G] = misc[1];
     if (n_end == (ival + 1) * (int64_t)M) p.ev_cnt[(int64_t)slot * p.n_groups + G] = 0;
