@@ -378,7 +378,12 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     return ((c & 0xFFFFu) << 3) | (c & 0xFFFF0000u);
   };
   auto tri_in = [&](int q) { return TriIn{c_a(q), c_b(q), w_l[q], u_l[q], Q_l[q], c_ch(q)}; };
-  auto prm = [&](int col, int64_t i) -> double { return UNI ? cst[C_PRM + col] : p.prm[col * p.n_nodes_total + i]; };
+  // uniform mechanism constants: FP32-mechanism kernels (registers to spare) take them straight from the kernel
+  // arguments, FP64 kernels from the LDS copy
+  constexpr bool KARG = std::is_same<S, float>::value;
+  auto prm = [&](int col, int64_t i) -> double {
+    return UNI ? (KARG ? p.prm_s[col] : cst[C_PRM + col]) : p.prm[col * p.n_nodes_total + i];
+  };
   StRec<S> *st = static_cast<StRec<S> *>(p.st);
   const SynRec<S> *syn = static_cast<const SynRec<S> *>(p.syn) + sb;
   S *sg = static_cast<S *>(p.syn_g) + sb;
@@ -510,9 +515,10 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     // the lower wave priority, so that a co-resident group's latency-bound sweeps issue ahead of it.
     __builtin_amdgcn_s_setprio(0);
     const bool pend = n > 0;
-    const S q10dt = (S)cst[C_Q10DT];
-    const S sdt = (S)cst[C_DT];
-    const S ca_fm = (S)cst[C_CA_FM], ca_fr = (S)cst[C_CA_FR], ca_k = (S)cst[C_CA_K];
+    const S q10dt = (S)(KARG ? p.q10dt : cst[C_Q10DT]);
+    const S sdt = (S)(KARG ? p.dt : cst[C_DT]);
+    const S ca_fm = (S)(KARG ? p.ca_fm : cst[C_CA_FM]), ca_fr = (S)(KARG ? p.ca_fr : cst[C_CA_FR]),
+            ca_k = (S)(KARG ? p.ca_k : cst[C_CA_K]);
     double od[K], orhs[K], odv[K];  // assembly results, written once every thread has read the staged synapses
 #pragma unroll
     for (int j = 0; j < K; ++j) {
