@@ -5,14 +5,16 @@
 // a workgroup can keep its group's voltages, synaptic conductances and the interval's events on chip for the whole
 // chunk and loop the per-step operations of Sec. 2 itself:
 //   A  deliver the events due at this step (sorted keys in LDS; one thread per synapse run, in key order);
+//   θ  threshold detection at each cell's soma for the previous step (Sec. 2), whose potentials are still on chip;
+//   S  per synapse: conductance and current at v_n staged in LDS;
 //   C  per compartment: advance the channel states with v_n (the state update of the previous step, done here so
 //      the states are read and written once per step), then the currents and analytic conductances at
 //      (v_n, states_n) into d and rhs (Sec. 2 matrix assembly; Sec. 3.5 CONDUCTANCE), point processes, background
 //      events drawn from a counter-based stream (Sec. 3.5, Random123), and the compartment's own axial terms;
 //   T  elimination from the leaves, one tree level at a time: each node gathers its children's contributions from
 //      LDS, then publishes its own (Sec. 2, Gaussian elimination of the tree; Sec. 4.4 constant-depth ordering);
-//   R  the roots: solve, update v, threshold detection (Sec. 2);
-//   B  back-substitution root to leaves, one level at a time, updating v.
+//   R  the roots (each cell rooted at a tree centre): solve, update v;
+//   B  back-substitution root to leaves, three levels per barrier, updating v.
 // At the end of the chunk the group's spikes fan out through their NetCons into the event ring (the spike exchange
 // of Sec. 2, here on one device).
 #include <hip/hip_runtime.h>
@@ -596,7 +598,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
           }
         }
         d += c_k(q);
-        double dvq = v;  // a root keeps its own potential for threshold detection
+        double dvq = v;  // a root carries its own potential: the root solve adds its x to it
         if (par >= 0) {
           dvq = V_l[par] - v;
           rhs -= c_b(q) * dvq;
