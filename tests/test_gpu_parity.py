@@ -225,6 +225,26 @@ def test_edge_shapes_kicks_and_clamps():
     assert_spikes_equal(orc, eng, min_count=3)
 
 
+@pytest.mark.parametrize("threads", [0, 512])
+def test_groups_of_many_small_cells(threads):
+    """400 two-compartment HH cells driven by somatic IClamps: groups of more than 64 cells, whose threshold tests
+    run on several waves (the chunk's spike count is read after all of them)"""
+    rng = np.random.default_rng(12)
+    n_cells = 400
+    parents = [[-1, 0]] * n_cells
+    diam = rng.uniform(0.5, 2.0, 2 * n_cells)
+    length = rng.uniform(10, 50, 2 * n_cells)
+    area = np.pi * diam * length
+    ri = TM.ri_uniform(diam, length)
+    soma = np.arange(0, 2 * n_cells, 2)
+    m = TM.make(parents, area, ri, {"hh": TM.hh(), "iclamp": TM.iclamp(soma, rng.uniform(0.002, 0.01, n_cells))})
+    say(f"400 two-compartment cells, 20 ms, group_threads {threads}")
+    orc, eng, worst = lockstep(m, range(40, 801, 40), group_threads=threads)
+    assert eng.info()["n_groups"] * 64 < n_cells  # more than 64 cells per group on average
+    assert worst <= 1.0, worst
+    assert_spikes_equal(orc, eng, min_count=200)
+
+
 def test_states_parity():
     m = synth.cortex_50k(n_cells=50, seed=8)
     say("states")
