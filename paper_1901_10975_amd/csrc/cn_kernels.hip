@@ -55,13 +55,13 @@ __device__ __forceinline__ double exp_tang(double x, const lds_table *exp_tab) {
 template <>
 struct Math<double> {
   static __device__ __forceinline__ double ex(double x, const lds_table *et) { return exp_tang(x, et); }
-  // reciprocal: hardware estimate refined by two Newton steps (error within an ulp or two of 1/x)
+  // reciprocal: the hardware estimate r (relative error eps below 2^-24) corrected to second order. With
+  // e = 1 - x r = eps (exact by fma), 1/x = r (1 + e + e^2 + ...), and r (1 + e + e^2) is off by eps^3 before its
+  // last rounding: the accuracy of two Newton steps in one operation fewer.
   static __device__ __forceinline__ double rcp(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, fma(e, e, e), r);
   }
   // 1 - exp(-z)
   static __device__ __forceinline__ double omx(double z, const lds_table *et) { return 1.0 - exp_tang(-z, et); }
@@ -75,7 +75,17 @@ struct Math<float> {
   static __device__ __forceinline__ float omx(float z, const lds_table *) { return 1.0f - __expf(-z); }
 };
 
-__device__ __forceinline__ double rcp64(double x) { return Math<double>::rcp(x); }
+// reciprocal of the tree solve: the FP64 kernels use Math<double>::rcp; the FP32-mechanism kernels keep two Newton
+// steps after the hardware estimate (the same accuracy; measured faster in their instruction mix)
+template <typename S>
+__device__ __forceinline__ double rcp64(double x) {
+  if (std::is_same<S, double>::value) return Math<double>::rcp(x);
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 
 constexpr double E_NEG_1P5 = 0.22313016014842982893;  // exp(-1.5)
 constexpr double E_POS_0P5 = 1.64872127070012814685;  // exp(0.5)
@@ -202,12 +212,13 @@ __device__ __forceinline__ void gather_children(uint32_t ch, int zero8, const do
 }
 
 // one node of the elimination: gather the children's contributions, then publish this node's own
+template <typename S>
 __device__ __forceinline__ void tri_node(int q, const TriIn &x, int zero8, double *w_l, double *u_l, double *P_l,
                                          double *Q_l) {
   double d = x.d, rhs = x.r;
   gather_children(x.ch, zero8, P_l, Q_l, d, rhs);
   const double adv = x.a * x.dv;  // off the dependency chain
-  const double ri = rcp64(d);
+  const double ri = rcp64<S>(d);
   const double w = ri * x.b, u = ri * rhs;
   w_l[q] = w;
   u_l[q] = u;
@@ -638,8 +649,8 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         const int lo_nn = L >= 2 ? LVB(L - 2) : 0;
         const int nq = lo_n + t;
         const TriIn nxt = tri_in(min(nq, N - 1));  // lanes past the level read the group's last node and ignore it
-        if (q < hi) tri_node(q, cur, NMAX * 8, w_l, u_l, P_l, Q_l);
-        for (int q2 = q + T; q2 < hi; q2 += T) tri_node(q2, tri_in(q2), NMAX * 8, w_l, u_l, P_l, Q_l);  // wide levels
+        if (q < hi) tri_node<S>(q, cur, NMAX * 8, w_l, u_l, P_l, Q_l);
+        for (int q2 = q + T; q2 < hi; q2 += T) tri_node<S>(q2, tri_in(q2), NMAX * 8, w_l, u_l, P_l, Q_l);  // wide levels
         __syncthreads();
         hi = lo;
         lo = lo_n;
@@ -652,7 +663,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         const TriIn x = q == t ? cur : tri_in(q);
         double d = x.d, rhs = x.r;
         gather_children(x.ch, NMAX * 8, P_l, Q_l, d, rhs);
-        const double xs = rhs * rcp64(d);
+        const double xs = rhs * rcp64<S>(d);
         const double vnew = x.dv + xs;
         P_l[q] = xs;
         V_l[q] = vnew;
@@ -724,14 +735,14 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     // the same sweeps without the look-ahead, for groups of 64 or more levels (level starts from LDS)
     auto plain_sweeps = [&]() {
       for (int L = D - 1; L >= 1; --L) {
-        for (int q = lv[L] + t; q < lv[L + 1]; q += T) tri_node(q, tri_in(q), NMAX * 8, w_l, u_l, P_l, Q_l);
+        for (int q = lv[L] + t; q < lv[L + 1]; q += T) tri_node<S>(q, tri_in(q), NMAX * 8, w_l, u_l, P_l, Q_l);
         __syncthreads();
       }
       for (int q = t; q < lv[1]; q += T) {
         const TriIn x = tri_in(q);
         double d = x.d, rhs = x.r;
         gather_children(x.ch, NMAX * 8, P_l, Q_l, d, rhs);
-        const double xs = rhs * rcp64(d);
+        const double xs = rhs * rcp64<S>(d);
         const double vnew = x.dv + xs;
         P_l[q] = xs;
         V_l[q] = vnew;
