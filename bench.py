@@ -1,12 +1,15 @@
 """Benchmark: compartment-timesteps per second of the fixed-step cable engine on one MI355X.
 
-Workload: cortex_50k - 50,000 cells with log-uniform 50..1000 compartments (15.93M compartments), hh + km + cahi in
-every compartment, 100 ExpSyn per cell fed by NetCons with delays U(1, 5) ms (1 ms minimum-delay interval, 40 steps
-of 0.025 ms) and 5 Hz Poisson background per synapse. Synthetic, seeded inputs (synth.cortex_50k).
+Main workload (the metric's configuration): cortex_50k - 50,000 cells with log-uniform 50..1000 compartments (15.93M
+compartments), hh + km + cahi in every compartment, 100 ExpSyn per cell fed by NetCons with delays U(1, 5) ms (1 ms
+minimum-delay interval, 40 steps of 0.025 ms) and 5 Hz Poisson background per synapse. Synthetic, seeded inputs
+(synth.cortex_50k).
 
 One benchmark step = one minimum-delay interval (40 time steps: delivery, mechanisms, assembly, tree solve,
-threshold detection, and the interval's spike fan-out). Inputs are resident in HBM before the timed region.
-The main line reports the FP64 path; the FP32-mechanism path is reported beside it.
+threshold detection, and the interval's spike fan-out). Inputs are resident in HBM before the timed region. The
+main line reports the FP64 path; beside it: the FP32-mechanism path on the same workload, the other workloads
+(clamped_cells, ring_network in both precisions, cortex_200k in both precisions) as microseconds per time step, the
+roofline of the dominant kernel and the oracle timed on the host cores.
 """
 import argparse
 import hashlib
@@ -19,11 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP64 vector peak: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops (FMA) x 2.4 GHz
-FP64_PEAK_TFLOPS = 78.6
-# algorithmic FP64 work per compartment-step of cortex_50k (hh, km, cahi rates and gates, currents, assembly and the
-# tree solve): about 500 lane operations, each exponential or divide counted as the operations it takes
-FLOPS_PER_COMP_STEP = 500.0
+# vector ALU lane-operation peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64 instruction issues over four
+# cycles; FP64 and unpacked FP32 instructions alike). The FP64 FLOP peak (78.6 TFLOP/s) counts an FMA as two.
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 PROFILE = os.path.join(ROOT, "profiles", "cn_interval_cortex50k_traffic.json")
 VALU_PROFILE = os.path.join(ROOT, "profiles", "cn_interval_cortex50k_valu.json")
 
@@ -51,46 +52,30 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(precision: str):
-    """HBM bytes per interval launch from the committed counter passes, or None when the kernel sources changed
-    since they were taken"""
+def _profile(path, precision):
+    """one kernel's record of a committed counter profile, or None when the kernel sources changed since it was
+    taken"""
     try:
-        with open(PROFILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except OSError:
         return None
     if rec.get("source_sha256") != kernel_sources_sha256():
         return None
-    k = rec.get("kernels", {}).get(precision)
-    return None if k is None else float(k["traffic_bytes"])
+    return rec.get("kernels", {}).get(precision)
 
 
-def profiled_valu(precision: str):
-    """VALU busy fraction and measured FP64 TFLOP/s of the interval kernel from the committed counter passes, or
-    None when the kernel sources changed since they were taken"""
-    try:
-        with open(VALU_PROFILE) as fh:
-            rec = json.load(fh)
-    except OSError:
-        return None
-    if rec.get("source_sha256") != kernel_sources_sha256():
-        return None
-    k = rec.get("kernels", {}).get(precision)
-    return None if k is None else {"valu_busy": k["valu_busy"], "measured_fp64_tflops": k["fp64_tflops"]}
-
-
-def run_gpu(m, precision, steps, warmup, log):
+def run_gpu(m, precision, steps, warmup, log, **kw):
     import torch
     from paper_1901_10975_amd import cn
 
     t0 = time.time()
-    eng = cn.Engine(m, precision=precision, timing=True, use_graph=True)
-    log(f"[bench] {precision}: model built in {time.time() - t0:.1f} s")
-    dt = m.dt
-    # warm-up (also fixes dt and captures the interval graph)
-    eng.run_to_step(0 + max(1, warmup) * 40)
+    eng = cn.Engine(m, precision=precision, timing=True, use_graph=True, **kw)
+    log(f"[bench] {m.name} {precision}: model built in {time.time() - t0:.1f} s")
+    eng.run_to_step(1)  # fixes dt, hence the interval length, and captures the interval graph
+    M = eng.info()["interval_steps"]
+    eng.run_to_step(max(1, warmup) * M)
     info = eng.info()
-    M = info["interval_steps"]
     n0 = info["step"]
     ms0, l0 = eng.stats()
     torch.cuda.synchronize()
@@ -105,74 +90,117 @@ def run_gpu(m, precision, steps, warmup, log):
     res = dict(wall=wall, M=M, steps=steps, kernel_ms=kernel_ms, launches=launches, info=info,
                n_spikes=int(g.size), comp_steps=float(m.n_comp) * steps * M)
     res["value"] = res["comp_steps"] / wall
-    log(f"[bench] {precision}: {steps} intervals x {M} steps in {wall:.3f} s -> {res['value']:.4e} comp-steps/s; "
-        f"interval kernel {kernel_ms:.3f} ms avg over {launches}; spikes so far {g.size}")
+    res["us_per_step"] = wall / (steps * M) * 1e6
+    log(f"[bench] {m.name} {precision}: {steps} intervals x {M} steps in {wall:.3f} s -> {res['value']:.4e} "
+        f"comp-steps/s ({res['us_per_step']:.2f} us/step); interval kernel {kernel_ms:.3f} ms avg over {launches}; "
+        f"spikes so far {g.size}")
     eng.close()
     return res
 
 
-def _oracle_rate(sub, threads, budget_s):
+def _oracle_rate(sub, threads, budget_s, M):
     """compartment-steps/s of the oracle on `sub`, advanced interval by interval until the time budget is used"""
     from oracle import oracle as O
 
-    orc = O.OracleSim(sub, n_threads=threads)
+    orc = O.OracleSim(sub, n_threads=threads, fast=True)
     n = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        n += 40
+        n += M
         orc.run_to_step(n)
     el = time.perf_counter() - t0
     return sub.n_comp * n / el, n, el
 
 
-def _cpu_model() -> str:
-    try:
-        with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
+def host_threads() -> int:
+    """the host cores this process may use: the OpenMP thread count the environment grants, else the affinity set"""
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        cores = min(cores, int(env))
+    return max(1, int(cores))
 
 
-def cpu_baseline(m, log, budget_s=12.0, budget_1_s=8.0):
-    """The oracle, as it stands, on the host cores over a bounded sample of the same workload: a random 5% of the
-    cells (with their synapses, background streams and the NetCons among them), advanced interval by interval until
-    the time budget is used; and on one core over a random 1% of the cells."""
+def cpu_baseline(m, M, log, budget_s=15.0, budget_1_s=8.0):
+    """The oracle, as it stands, on every host core granted to this process over a bounded sample of the same
+    workload: a random 5% of the cells (with their synapses, background streams and the NetCons among them),
+    advanced interval by interval until the time budget is used; and on one core over a random 1% of the cells.
+    Timed with the oracle compiled -O3 -march=native for this host (no FMA contraction)."""
     import numpy as np
 
+    from oracle import oracle as O
     from paper_1901_10975_amd import synth
 
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(int(cores), 16))
+    O.build_fast()
+    cores = host_threads()
     rng = np.random.default_rng(0)
     cells = np.sort(rng.choice(m.n_cells, max(1, m.n_cells // 20), replace=False))
     sub = synth.subset_cells(m, cells)
-    val, n, el = _oracle_rate(sub, cores, budget_s)
+    val, n, el = _oracle_rate(sub, cores, budget_s, M)
     log(f"[bench] oracle: {sub.n_cells} cells / {sub.n_comp} compartments x {n} steps in {el:.1f} s on {cores} "
         f"threads -> {val:.3e} comp-steps/s")
     cells1 = np.sort(rng.choice(m.n_cells, max(1, m.n_cells // 100), replace=False))
     sub1 = synth.subset_cells(m, cells1)
-    val1, n1, el1 = _oracle_rate(sub1, 1, budget_1_s)
+    val1, n1, el1 = _oracle_rate(sub1, 1, budget_1_s, M)
     log(f"[bench] oracle: {sub1.n_cells} cells / {sub1.n_comp} compartments x {n1} steps in {el1:.1f} s on 1 "
         f"thread -> {val1:.3e} comp-steps/s")
     return {"value": val, "unit": "compartment-timesteps/s", "cores": cores, "kind": "oracle",
             "sample": f"{sub.n_cells} random cells of the workload ({sub.n_comp} compartments, their synapses, "
-                      f"background streams and internal NetCons), {n} steps of 0.025 ms, FP64, {cores} threads",
-            "cpu_model": _cpu_model(),
+                      f"background streams and internal NetCons), {n} steps of 0.025 ms, FP64, {cores} threads, "
+                      f"oracle built -O3 -march=native -ffp-contract=off",
+            "cpu_model": O.cpu_model(), "host_cpus_visible": os.cpu_count(),
             "single_core": {"value": val1, "cores": 1,
                             "sample": f"{sub1.n_cells} random cells ({sub1.n_comp} compartments), {n1} steps, FP64"}}
+
+
+def roofline(m, r64, fp32_res=None):
+    """Roofline object of the dominant kernel (the FP64 interval kernel). achieved = the per-step method's
+    algorithmic HBM bytes of one launch (bytes_per_step x steps per launch) / the launch's mean duration, against the
+    8 TB/s HBM peak; traffic = measured HBM bytes per launch from the committed counter passes (null once the kernel
+    changed). The kernel keeps a group on chip for a whole interval, so it moves far fewer bytes than the byte model
+    counts; the vector-ALU view (measured VALU lane instructions against the lane-operation peak) is reported beside
+    it and becomes the bound if the byte-model fraction would exceed one."""
+    per_launch = bytes_per_step(m, False) * r64["M"]
+    kern_s = r64["kernel_ms"] * 1e-3
+    eff_gbs = per_launch / kern_s / 1e9
+    tr = _profile(PROFILE, "fp64")
+    traffic = None if tr is None else float(tr["traffic_bytes"])
+    cnt = _profile(VALU_PROFILE, "fp64")
+    alu = None
+    if cnt is not None:
+        lane = float(cnt["valu_lane_insts_per_comp_step"]) * m.n_comp * r64["M"] / kern_s
+        alu = {"bound": "alu", "achieved": lane / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
+               "unit": "T VALU lane-instructions/s", "frac": lane / VALU_PEAK_LANE_OPS,
+               "valu_busy": cnt["valu_busy"], "fp64_tflops_counted": cnt["fp64_tflops"],
+               "valu_lane_instr_per_comp_step": cnt["valu_lane_insts_per_comp_step"]}
+    hbm = {"bound": "hbm", "achieved": eff_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": eff_gbs / HBM_PEAK_GBS,
+           "traffic": traffic, "algorithmic_bytes_per_launch": per_launch,
+           "bytes_per_unit": "140 B per compartment-step + 28 B per synapse-step (FP64)"}
+    out = dict(hbm)
+    if hbm["frac"] > 1.0 and alu is not None:
+        out = dict(alu)
+        out["traffic"] = traffic
+        out["hbm_byte_model"] = hbm
+    else:
+        out["alu"] = alu
+    out["kernel"] = "cn_interval<%d,%d,double>" % (r64["info"]["group_threads"], r64["info"]["group_slots"])
+    out["kernel_ms"] = r64["kernel_ms"]
+    out["measured_hbm_GBs"] = None if traffic is None else traffic / kern_s / 1e9
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100, help="timed minimum-delay intervals (40 steps each)")
+    ap.add_argument("--steps", type=int, default=100, help="timed minimum-delay intervals of the main workload")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n-cells", type=int, default=50000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip clamped_cells, ring_network and cortex_200k")
+    ap.add_argument("--only", choices=["cortex_50k", "cortex_200k"], default=None,
+                    help="run one workload in both precisions and print its line only")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -199,6 +227,15 @@ def main():
         log(f"[bench] copy probe: {a.numel() * 4} bytes read and written")
         del a, b
 
+    if args.only == "cortex_200k":
+        m = synth.cortex_200k()
+        log(f"[bench] cortex_200k: {m.n_cells} cells, {m.n_comp} compartments, {m.n_syn} synapses")
+        r64 = run_gpu(m, "fp64", args.steps, args.warmup, log)
+        r32 = run_gpu(m, "fp32_mech", args.steps, args.warmup, log)
+        print(json.dumps({"workload": "cortex_200k", "n_comp": m.n_comp, "fp64": _brief(r64, m),
+                          "fp32_mech": _brief(r32, m, True)}), flush=True)
+        return
+
     t0 = time.time()
     m = synth.cortex_50k(n_cells=args.n_cells)
     log(f"[bench] cortex_50k: {m.n_cells} cells, {m.n_comp} compartments, {m.n_syn} synapses "
@@ -206,13 +243,6 @@ def main():
     r64 = run_gpu(m, "fp64", args.steps, args.warmup, log)
     r32 = None if args.no_fp32 else run_gpu(m, "fp32_mech", args.steps, args.warmup, log)
 
-    bps = bytes_per_step(m, False)
-    per_launch = bps * r64["M"]
-    kern_s = r64["kernel_ms"] * 1e-3
-    eff_gbs = per_launch / kern_s / 1e9  # the per-step method's bytes at this rate
-    flops_launch = FLOPS_PER_COMP_STEP * m.n_comp * r64["M"]
-    achieved = flops_launch / kern_s / 1e12
-    traffic = profiled_traffic("fp64")
     out = {
         "metric": "compartment-timesteps/sec at 50k cells (FP64 vs FP32-mech); HBM GB/s fraction",
         "value": r64["value"],
@@ -229,30 +259,77 @@ def main():
         "config": {"workload": "cortex_50k: 50000 cells, log-uniform 50-1000 compartments (%d total), hh+km+cahi, "
                                "100 ExpSyn/cell, NetCon delay U(1,5) ms, Poisson 5 Hz, dt 0.025 ms; one step = one "
                                "1 ms min-delay interval (40 time steps)" % m.n_comp,
-                   "n_cells": m.n_cells, "n_comp": m.n_comp, "n_syn": m.n_syn, "interval_steps": r64["M"]},
-        # The interval kernel keeps a group's potentials, states and constants on chip for all M steps, so it moves
-        # far fewer HBM bytes than the per-step method: the bound is FP64 vector arithmetic and the latency of the
-        # tree sweeps, not HBM. traffic = measured HBM bytes per launch (calibrated counters).
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "cn_interval<%d,%d,double>" % (r64["info"]["group_threads"], r64["info"]["group_slots"]),
-                     "kernel_ms": r64["kernel_ms"], "flops_per_launch": flops_launch,
-                     "measured_hbm_GBs": None if traffic is None else traffic / kern_s / 1e9,
-                     "effective_hbm_GBs": eff_gbs, "effective_hbm_frac": eff_gbs / HBM_PEAK_GBS,
-                     "per_step_method_bytes_per_launch": per_launch,
-                     "counters": profiled_valu("fp64")},
+                   "n_cells": m.n_cells, "n_comp": m.n_comp, "n_syn": m.n_syn, "interval_steps": r64["M"],
+                   "group_threads": r64["info"]["group_threads"], "group_slots": r64["info"]["group_slots"]},
+        "us_per_time_step": r64["us_per_step"],
+        "roofline": roofline(m, r64),
     }
     if r32 is not None:
-        bps32 = bytes_per_step(m, True)
-        out["fp32_mech"] = {"value": r32["value"], "ms_per_step": r32["wall"] / args.steps * 1e3,
-                            "kernel_ms": r32["kernel_ms"],
-                            "speedup_vs_fp64": r32["value"] / r64["value"],
-                            "effective_GBs": bps32 * r32["M"] / (r32["kernel_ms"] * 1e-3) / 1e9,
-                            "traffic": profiled_traffic("fp32_mech"), "counters": profiled_valu("fp32_mech")}
+        out["fp32_mech"] = _brief(r32, m, True)
+        out["fp32_mech"]["speedup_vs_fp64"] = r32["value"] / r64["value"]
+        out["fp32_mech"]["meets_1p5x_target"] = bool(r32["value"] / r64["value"] >= 1.5)
+    if not args.no_other_configs and args.only is None:
+        out["other_configs"] = other_configs(log, synth)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m, log)
+        out["cpu_baseline"] = cpu_baseline(m, r64["M"], log)
         out["cpu_baseline"]["gpu_over_oracle"] = r64["value"] / out["cpu_baseline"]["value"]
     print(json.dumps(out), flush=True)
+
+
+def _brief(r, m, fp32=False):
+    bps = bytes_per_step(m, fp32)
+    return {"value": r["value"], "unit": "compartment-timesteps/s", "us_per_time_step": r["us_per_step"],
+            "interval_steps": r["M"], "kernel_ms": r["kernel_ms"],
+            "effective_hbm_frac": bps * r["M"] / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "counters": _profile(VALU_PROFILE, "fp32_mech" if fp32 else "fp64")}
+
+
+def other_configs(log, synth):
+    """the remaining workloads: clamped_cells (64 x 32, 100 ms), ring_network (1000 x 200, 200 ms FP64; 100 ms in the
+    FP32-mechanism path), cortex_200k (200,000 cells, 50 ms, both precisions). The small ones fit in L2 or the
+    Infinity Cache: their figure is microseconds per time step."""
+    res = {}
+    for name, make, prec, tstop in (("clamped_cells", synth.clamped_cells, "fp64", 100.0),
+                                    ("ring_network", synth.ring_network, "fp64", 200.0),
+                                    ("ring_network_fp32_mech", synth.ring_network, "fp32_mech", 100.0)):
+        m = make()
+        r = run_gpu_whole(m, prec, tstop, log)
+        res[name] = r
+    m = synth.cortex_200k()
+    log(f"[bench] cortex_200k: {m.n_cells} cells, {m.n_comp} compartments, {m.n_syn} synapses")
+    for prec in ("fp64", "fp32_mech"):
+        r = run_gpu(m, prec, 100, 2, log)
+        res["cortex_200k_" + prec] = _brief(r, m, prec == "fp32_mech")
+    res["cortex_200k_fp32_mech"]["speedup_vs_fp64"] = (res["cortex_200k_fp32_mech"]["value"]
+                                                       / res["cortex_200k_fp64"]["value"])
+    return res
+
+
+def run_gpu_whole(m, precision, tstop, log):
+    """a whole run of a small workload (warm-up: a short throw-away run), timed end to end"""
+    import torch
+    from paper_1901_10975_amd import cn
+
+    w = cn.Engine(m, precision=precision)
+    w.run(2.0)
+    w.close()
+    eng = cn.Engine(m, precision=precision, timing=True)
+    eng.run_to_step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eng.run(tstop)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n = int(round(tstop / m.dt)) - 1
+    g, _, _ = eng.spikes()
+    ms, launches = eng.stats()
+    r = {"us_per_time_step": wall / n * 1e6, "steps": n, "value": m.n_comp * n / wall,
+         "unit": "compartment-timesteps/s", "precision": precision, "n_comp": m.n_comp, "spikes": int(g.size),
+         "interval_steps": eng.info()["interval_steps"], "kernel_ms_mean": ms / max(1, launches)}
+    log(f"[bench] {m.name} {precision}: {tstop} ms = {n} steps in {wall:.3f} s -> {r['us_per_time_step']:.2f} "
+        f"us/step, {g.size} spikes")
+    eng.close()
+    return r
 
 
 if __name__ == "__main__":

@@ -128,7 +128,10 @@ typedef struct cn_options {
   int32_t timing;         /* 1: time the interval kernel with HIP events (see cn_stats) */
   int32_t validate_only;  /* 1: build and check the device layout on the host only, touching no device; the model
                              then answers cn_model_info and nothing else (cn_run returns CN_E_STATE) */
-  int32_t reserved[6];
+  int32_t fault_inject;   /* tests of the error paths only (0 in normal use): 1 makes the first spike-record drain of
+                             cn_run report a device failure after real work was queued; 2 makes the graph capture
+                             fail after it began */
+  int32_t reserved[5];
 } cn_options;
 
 typedef struct cn_model cn_model;

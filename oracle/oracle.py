@@ -17,6 +17,10 @@ LIB_PATH = os.path.join(HERE, "liborc.so")
 # The same source compiled with fused multiply-add contraction: an equally valid oracle that rounds differently at
 # every step. Tests use it to measure how strongly a network amplifies rounding-level differences.
 LIB_FMA_PATH = os.path.join(HERE, "liborc_fma.so")
+# The same source optimised for the host that times it (-O3 -march=native, still without FMA contraction): used only
+# to time the oracle beside the GPU. It is compiled on the timing host itself; the CPU model it was built for is
+# recorded next to it and a different host rebuilds it.
+LIB_FAST_PATH = os.path.join(HERE, "liborc_fast.so")
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -54,13 +58,41 @@ def build(force: bool = True) -> str:
     return LIB_PATH
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def build_fast() -> str:
+    """Compile liborc_fast.so for this host unless it was already built here."""
+    tag = LIB_FAST_PATH + ".cpu"
+    want = cpu_model()
+    if os.path.exists(LIB_FAST_PATH) and os.path.exists(tag) and open(tag).read() == want:
+        return LIB_FAST_PATH
+    cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-Wall", "-Wno-unused-function", os.path.join(HERE, "orc.c"), "-o", LIB_FAST_PATH + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_FAST_PATH + ".tmp", LIB_FAST_PATH)
+    with open(tag, "w") as fh:
+        fh.write(want)
+    return LIB_FAST_PATH
+
+
 _libs = {}
 
 
-def lib(fma: bool = False):
-    path = LIB_FMA_PATH if fma else LIB_PATH
+def lib(fma: bool = False, fast: bool = False):
+    path = LIB_FAST_PATH if fast else (LIB_FMA_PATH if fma else LIB_PATH)
     if path not in _libs:
-        if not os.path.exists(path):
+        if fast:
+            build_fast()
+        elif not os.path.exists(path):
             build(force=False)
         L = C.CDLL(path)
         L.orc_error.restype = C.c_char_p
@@ -96,9 +128,9 @@ class OracleSim:
     """One oracle simulation of a ``synth.Model``. ``batch_steps``: 0 inserts a spike's events at once; M > 0
     inserts them at the end of each M-step interval."""
 
-    def __init__(self, model, dt=None, batch_steps=0, n_threads=1, keep_matrix=False, fma=False):
+    def __init__(self, model, dt=None, batch_steps=0, n_threads=1, keep_matrix=False, fma=False, fast=False):
         self.model = model
-        self._L = lib(fma)
+        self._L = lib(fma, fast)
         dt = float(model.dt if dt is None else dt)
         n = model.n_comp
         keep = []

@@ -59,7 +59,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("layout", C.c_int32), ("stream", C.c_void_p), ("dev_alloc", ALLOC_FN),
                 ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p), ("event_capacity", C.c_int32),
                 ("max_interval", C.c_int32), ("group_threads", C.c_int32), ("use_graph", C.c_int32),
-                ("timing", C.c_int32), ("validate_only", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("timing", C.c_int32), ("validate_only", C.c_int32), ("fault_inject", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class Info(C.Structure):
@@ -143,7 +144,7 @@ class Engine:
 
     def __init__(self, model: "synth.Model", precision: str = "fp64", use_graph: bool = True, timing: bool = False,
                  event_capacity: int = 0, max_interval: int = 0, group_threads: int = 0, use_torch: bool = True,
-                 stream=None, validate_only: bool = False):
+                 stream=None, validate_only: bool = False, fault_inject: int = 0):
         L = lib()
         self.model = model
         self.dt = float(model.dt)
@@ -194,6 +195,7 @@ class Engine:
         opt.use_graph = 1 if use_graph else 0
         opt.timing = 1 if timing else 0
         opt.validate_only = 1 if validate_only else 0
+        opt.fault_inject = int(fault_inject)
         self._mem = None
         if use_torch and not validate_only:
             import torch

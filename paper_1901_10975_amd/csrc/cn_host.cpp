@@ -992,10 +992,17 @@ static void prepare_dt(cn_model *m, double dt) {
   HIPCHK(hipStreamSynchronize(m->stream));
   if (m->opt.use_graph) {
     HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
+    // whatever fails below, the capture is ended before the error is reported, so that the caller's stream never
+    // stays in capture mode
     hipError_t e1 = launch_interval(m->kp, m->fp32, m->threads, m->slots, m->lds_bytes, m->stream);
     if (e1 == hipSuccess) e1 = launch_fanout(m->kp, m->stream);
     hipError_t e2 = launch_advance(p.ctl, p.M, m->stream);
+    if (m->opt.fault_inject == 2 && e2 == hipSuccess) e2 = hipErrorLaunchFailure;
     hipError_t e3 = hipStreamEndCapture(m->stream, &m->graph);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+      if (m->graph) (void)hipGraphDestroy(m->graph);
+      m->graph = nullptr;
+    }
     HIPCHK(e1);
     HIPCHK(e2);
     HIPCHK(e3);
@@ -1006,6 +1013,7 @@ static void prepare_dt(cn_model *m, double dt) {
 static void drain(cn_model *m, int32_t n_timed) {
   KParams &p = m->kp;
   HIPCHK(hipStreamSynchronize(m->stream));
+  if (m->opt.fault_inject == 1) HIPCHK(hipErrorLaunchFailure);
   int32_t cnt = 0, flags[4];
   HIPCHK(hipMemcpy(&cnt, p.rec_cnt, sizeof cnt, hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(flags, p.flags, sizeof flags, hipMemcpyDeviceToHost));
@@ -1124,18 +1132,24 @@ int cn_run(cn_model *m, double tstop, double dt) {
   if (m->broken) return fail(CN_E_STATE, "model is in an error state after a failed run");
   if (m->dry) return fail(CN_E_STATE, "model was built with validate_only");
   if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(tstop)) return fail(CN_E_INVALID, "bad tstop or dt");
+  if (m->dt_fixed && dt != m->dt) return fail(CN_E_STATE, "dt differs from the first cn_run call");
+  const double nd = tstop / dt;
+  if (!(std::fabs(nd) < 9.0e18)) return fail(CN_E_INVALID, "tstop / dt out of range");
+  const int64_t N = llround(nd);
+  if (N < m->step) return fail(CN_E_STATE, "tstop lies before the current time");
+  // From the first device call on, a failure leaves the device state (potentials, states, event ring, spike record)
+  // out of step with the host's step counter: the model is then marked broken and refuses further runs.
+  bool touched = false;
   try {
     if (!m->dt_fixed) {
+      touched = true;
       prepare_dt(m, dt);
       m->dt = dt;
       m->dt_fixed = true;
-    } else if (dt != m->dt) {
-      return fail(CN_E_STATE, "dt differs from the first cn_run call");
     }
-    const int64_t N = llround(tstop / dt);
-    if (N < m->step) return fail(CN_E_STATE, "tstop lies before the current time");
     if (N == m->step) return CN_OK;
     KParams &p = m->kp;
+    touched = true;
     HIPCHK(launch_set_ctl(p.ctl, m->step, N, m->stream));
     const bool timing = m->opt.timing != 0;
     if (timing && (int32_t)m->ev_pool.size() < 2 * m->drain_every) {
@@ -1166,10 +1180,13 @@ int cn_run(cn_model *m, double tstop, double dt) {
     }
     m->step = N;
   } catch (const Err &e) {
+    if (touched) m->broken = true;
     return fail(e.code, e.msg);
   } catch (const std::bad_alloc &) {
+    if (touched) m->broken = true;
     return fail(CN_E_NOMEM, "out of host memory");
   } catch (...) {
+    if (touched) m->broken = true;
     return fail(CN_E_DEVICE, "unexpected failure in cn_run");
   }
   return CN_OK;

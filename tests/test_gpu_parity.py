@@ -60,13 +60,18 @@ def _ensemble(m):
     return out
 
 
-def lockstep(m, checkpoints, precision="fp64", sensitivity=True, **kw):
+def lockstep(m, checkpoints, precision="fp64", sensitivity=True, spikes_each=False, **kw):
     """run the oracle, its rounding-level variants and the GPU in lockstep; returns the oracle, the engine and the
-    worst ratio dev(t) / bar(t) (<= 1 passes)"""
+    worst ratio dev(t) / bar(t) (<= 1 passes). sensitivity: True for the whole ensemble, "fma" for the FMA-built
+    oracle alone (large models), False for the plain 1e-10 bar. spikes_each: compare the spike lists at every
+    checkpoint."""
     orc = O.OracleSim(m, n_threads=THREADS)
-    ens = _ensemble(m) if sensitivity else []
+    if sensitivity == "fma":
+        ens = [O.OracleSim(m, n_threads=THREADS, fma=True)]
+    else:
+        ens = _ensemble(m) if sensitivity else []
     eng = _engine(m, precision=precision, **kw)
-    worst = 0.0
+    worst, ratios = 0.0, []
     for n in checkpoints:
         orc.run_to_step(n)
         eng.run_to_step(n)
@@ -80,6 +85,14 @@ def lockstep(m, checkpoints, precision="fp64", sensitivity=True, **kw):
         if dev / bar > worst:
             say(f"  step {n}: dev {dev:.2e} sensitivity {s:.2e} bar {bar:.2e}")
         worst = max(worst, dev / bar)
+        if s > 0.0:
+            ratios.append(dev / s)
+        if spikes_each:
+            go, so, _ = orc.spikes()
+            gg, sg, _ = eng.spikes()
+            assert np.array_equal(go, gg) and np.array_equal(so, sg), f"spike lists differ at step {n}"
+    if ratios:
+        say(f"  worst dev/s(t) {max(ratios):.2f}, median {float(np.median(ratios)):.2f}")
     orc.sens_t = 0.0
     g1, s1, t1 = orc.spikes()
     for e in ens:
@@ -105,12 +118,37 @@ def test_clamped_cells_full():
     assert_spikes_equal(orc, eng, min_count=10)
 
 
-def test_ring_network_100ms():
+def test_ring_network_200ms():
+    """the ring network over its full 200 ms"""
     m = synth.ring_network()
-    say("ring_network 1000x200 100 ms")
-    orc, eng, worst = lockstep(m, range(200, 4001, 200))
+    say("ring_network 1000x200 200 ms")
+    orc, eng, worst = lockstep(m, range(200, 8001, 200))
     assert worst <= 1.0, worst
     assert_spikes_equal(orc, eng, min_count=100)
+
+
+def test_ring_network_plain_bar_first_25ms():
+    """over the window in which the network's rounding sensitivity stays far below 1e-10, the plain bar: voltages
+    within 1e-10 relative at every interval boundary, spikes identical"""
+    m = synth.ring_network()
+    say("ring_network 1000x200, 25 ms, plain 1e-10 bar")
+    orc, eng, worst = lockstep(m, range(40, 1001, 40), sensitivity=False, spikes_each=True)
+    assert worst <= 1.0, worst
+    assert_spikes_equal(orc, eng, min_count=5)
+
+
+@pytest.mark.timeout(900)
+def test_full_size_cortex_50k_20ms_every_compartment():
+    """cortex_50k at full size (50,000 cells, 15.9M compartments, 5M synapses, Poisson background) in the
+    benchmark's launch configuration over 20 ms (20 minimum-delay intervals, NetCon events crossing groups): every
+    compartment and the whole spike list against the oracle at every interval boundary. The rounding sensitivity
+    comes from the FMA-built oracle alone (the full ensemble would take five oracle runs of the whole network)."""
+    m = synth.cortex_50k()
+    say(f"cortex_50k full size, {m.n_comp} compartments, 20 ms, every interval boundary")
+    orc, eng, worst = lockstep(m, range(40, 801, 40), sensitivity="fma", spikes_each=True)
+    assert worst <= 1.0, worst
+    assert_spikes_equal(orc, eng, min_count=1)
+    say(f"  {orc.spikes()[0].size} spikes identical")
 
 
 @pytest.mark.parametrize("threads", [0, 512])
