@@ -116,6 +116,9 @@ def lib(fma: bool = False, fast: bool = False):
         L.orc_poisson_draw.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64]
         L.orc_poisson_draw.restype = C.c_uint32
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+        L.orc_restore.argtypes = [C.c_void_p, C.c_int64] + [_dp] * 8 + [C.c_int64, _i32p, _i64p]
+        L.orc_restore.restype = C.c_int
+        L.orc_set_seed.argtypes = [C.c_void_p, C.c_uint64]
         _libs[path] = L
     return _libs[path]
 
@@ -237,6 +240,28 @@ class OracleSim:
         self._L.orc_get_states(self._h, *[_p(out[k], C.c_double) for k in
                                         ("hh_m", "hh_h", "hh_n", "km_n", "cahi_m", "cahi_cai", "syn_g")])
         return out
+
+    def checkpoint(self) -> dict:
+        """the state a restart needs: step, potentials, mechanism states, conductances and the spikes so far"""
+        gid, step, t = self.spikes()
+        return dict(step=self.step, v=self.v(), states=self.states(), gid=gid, spike_step=step)
+
+    def restore(self, ck: dict):
+        """continue from `ck` (as checkpoint() returns it) in this model, which must not have run yet"""
+        st = ck["states"]
+        keys = ("hh_m", "hh_h", "hh_n", "km_n", "cahi_m", "cahi_cai", "syn_g")
+        arrs = [np.ascontiguousarray(st[k], np.float64) for k in keys]
+        v = np.ascontiguousarray(ck["v"], np.float64)
+        gid = np.ascontiguousarray(ck["gid"], np.int32)
+        stp = np.ascontiguousarray(ck["spike_step"], np.int64)
+        rc = self._L.orc_restore(self._h, int(ck["step"]), _p(v, C.c_double), *[_p(a, C.c_double) for a in arrs],
+                                 int(gid.size), _p(gid, C.c_int32), _p(stp, C.c_int64))
+        if rc != 0:
+            raise RuntimeError("oracle: " + self._L.orc_error().decode())
+
+    def set_seed(self, seed: int):
+        """key of the background streams from the current step on"""
+        self._L.orc_set_seed(self._h, int(seed) & 0xFFFFFFFFFFFFFFFF)
 
     def last_matrix(self):
         n = self.model.n_comp

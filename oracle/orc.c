@@ -623,6 +623,46 @@ int orc_run(orc_model *m, int64_t n_target) {
   return 0;
 }
 
+/* Checkpoint-restart (Sec. 3.4): a run continues from a saved state - the step, the potentials, the mechanism
+ * states and the synaptic conductances - with the events that were still travelling at the checkpoint recovered
+ * from the spikes that sent them, instead of a saved event queue: every NetCon of a given spike (gid, k) whose
+ * arrival step k + D lies at or after the restart step is queued again. The model must not have run yet. */
+int orc_restore(orc_model *m, int64_t step, const double *v, const double *hh_m, const double *hh_h,
+                const double *hh_n, const double *km_n, const double *cahi_m, const double *cahi_cai,
+                const double *syn_g, int64_t n_spk, const int32_t *spk_gid, const int64_t *spk_step) {
+  if (!m) { set_err("null model"); return -1; }
+  if (m->step != 0 || m->sp_gid.n != 0) { set_err("restore needs a model that has not run"); return -1; }
+  if (step < 0) { set_err("negative restart step"); return -1; }
+  memcpy(m->v, v, (size_t)m->n_comp * sizeof(double));
+  if (m->n_hh) {
+    memcpy(m->hm, hh_m, (size_t)m->n_hh * sizeof(double));
+    memcpy(m->hh, hh_h, (size_t)m->n_hh * sizeof(double));
+    memcpy(m->hn, hh_n, (size_t)m->n_hh * sizeof(double));
+  }
+  if (m->n_km) memcpy(m->km_n, km_n, (size_t)m->n_km * sizeof(double));
+  if (m->n_cahi) {
+    memcpy(m->ca_m, cahi_m, (size_t)m->n_cahi * sizeof(double));
+    memcpy(m->ca_cai, cahi_cai, (size_t)m->n_cahi * sizeof(double));
+  }
+  if (m->n_syn) memcpy(m->syn_g, syn_g, (size_t)m->n_syn * sizeof(double));
+  for (int64_t q = 0; q < n_spk; ++q) {
+    const int64_t gid = spk_gid[q], k = spk_step[q];
+    if (gid < 0 || gid >= m->n_cells || k > step) { set_err("bad checkpoint spike"); return -1; }
+    for (int64_t o = m->out_off[gid]; o < m->out_off[gid + 1]; ++o) {
+      const int64_t nc = m->out_nc[o];
+      const int64_t due = k + m->nc_D[nc];
+      if (due < step) continue; /* delivered before the checkpoint */
+      if (due - step >= m->Q) { set_err("checkpoint spike beyond the event horizon"); return -1; }
+      if (iv_push(&m->ring[due % m->Q], nc)) { set_err("out of memory"); return -1; }
+    }
+  }
+  m->step = step;
+  return 0;
+}
+
+/* new key for the background streams from the current step on (a restart with other random streams) */
+void orc_set_seed(orc_model *m, uint64_t seed) { m->seed = seed; }
+
 int64_t orc_step(const orc_model *m) { return m->step; }
 int64_t orc_n_spikes(const orc_model *m) { return m->sp_gid.n; }
 int64_t orc_n_delivered(const orc_model *m) { return m->n_delivered; }

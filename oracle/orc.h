@@ -79,6 +79,15 @@ void orc_get_last_matrix(const orc_model *m, double *d, double *rhs, double *dv)
 /* number of network events delivered so far (kicks + NetCon events + background events) */
 int64_t orc_n_delivered(const orc_model *m);
 
+/* Checkpoint-restart (Sec. 3.4): continue from a saved step, potentials, mechanism states and conductances (arrays
+ * laid out as orc_get_v / orc_get_states give them; NULL for absent mechanisms); the events still in flight at that
+ * step are re-queued from the spikes (gid, step) that sent them. The model must not have run. 0 or -1. */
+int orc_restore(orc_model *m, int64_t step, const double *v, const double *hh_m, const double *hh_h,
+                const double *hh_n, const double *km_n, const double *cahi_m, const double *cahi_cai,
+                const double *syn_g, int64_t n_spk, const int32_t *spk_gid, const int64_t *spk_step);
+/* key of the background streams from the current step on */
+void orc_set_seed(orc_model *m, uint64_t seed);
+
 /* Test hooks.
  * Hines elimination of one tree of n nodes in place (Sec. 2; Sec. 4.4 on its operation count): on return rhs
  * holds the solution. Returns the number of floating-point operations performed. */

@@ -4,6 +4,7 @@ Each test checks the oracle against something other than itself: a library solve
 every tree shape, the closed form of the discrete scheme, an invariant of the equations, an independent integrator
 of the continuous model, or values printed in the literature.
 """
+import copy
 import dataclasses
 import itertools
 
@@ -664,3 +665,69 @@ def test_k_partition_equals_unpartitioned():
         assert passes >= 3  # remote spikes changed the partitions' runs
         assert sorted((s[1], s[0], s[2]) for s in spikes) == ref
         assert np.array_equal(v, a.v())
+
+
+def _active_ring(n_cells=120, n_comp=40, seed=21):
+    """a small ring-recipe network with weights raised tenfold, so that spikes keep travelling between cells"""
+    m = synth.ring_network(n_cells=n_cells, n_comp=n_comp, seed=seed, tstop=60.0)
+    m.nc_weight = m.nc_weight * 10.0
+    return m
+
+
+@pytest.mark.parametrize("n0", [800, 813])
+def test_checkpoint_restart_equals_one_run(n0):
+    """Checkpoint-restart (Sec. 3.4): a run saved at step n0 - potentials, states, conductances and its spikes - and
+    continued in a fresh model reproduces the uninterrupted run bitwise, at an interval boundary and mid-interval.
+    The events in flight at n0 are rebuilt from the spikes that sent them: without those spikes the continuation
+    differs, so the collapse of the queue into its firing spikes is what the equality checks."""
+    m = _active_ring()
+    N = 2400
+    one = O.OracleSim(m, batch_steps=40)
+    one.run_to_step(N)
+    a = O.OracleSim(m, batch_steps=40)
+    a.run_to_step(n0)
+    ck = a.checkpoint()
+    ga, sa, _ = a.spikes()
+    in_flight = [(g, s) for g, s in zip(ga, sa) if s + 1.0 / m.dt > n0]  # sent within the shortest delay
+    assert len(in_flight) > 0
+    b = O.OracleSim(m, batch_steps=40)
+    b.restore(ck)
+    b.run_to_step(N)
+    assert np.array_equal(b.v(), one.v())
+    g1, s1, t1 = one.spikes()
+    gb, sb, tb = b.spikes()
+    after = s1 > n0
+    assert np.array_equal(gb, g1[after]) and np.array_equal(sb, s1[after]) and np.array_equal(tb, t1[after])
+    for k, x in one.states().items():
+        assert np.array_equal(b.states()[k], x), k
+    c = O.OracleSim(m, batch_steps=40)
+    ck_lost = dict(ck, gid=ck["gid"][:0], spike_step=ck["spike_step"][:0])
+    c.restore(ck_lost)
+    c.run_to_step(N)
+    assert not np.array_equal(c.v(), one.v())
+
+
+def test_restart_with_new_background_streams():
+    """a restart under another seed: the saved state continues with the new streams; the same as reseeding the
+    uninterrupted run at the checkpoint, and different from the old streams after it"""
+    m = synth.cortex_50k(n_cells=40, seed=9)
+    n0, N = 400, 1200
+    a = O.OracleSim(m)
+    a.run_to_step(n0)
+    ck = a.checkpoint()
+    ref = O.OracleSim(m)
+    ref.run_to_step(n0)
+    ref.set_seed(777)
+    ref.run_to_step(N)
+    m2 = copy.copy(m)
+    m2.seed = 777
+    b = O.OracleSim(m2)
+    b.restore(ck)
+    b.run_to_step(N)
+    assert np.array_equal(b.v(), ref.v())
+    a.run_to_step(N)
+    assert not np.array_equal(a.v(), ref.v())
+    ok = O.OracleSim(m)
+    with pytest.raises(RuntimeError):
+        ok.run_to_step(1)
+        ok.restore(ck)  # a model that has run
