@@ -119,6 +119,7 @@ def lib(fma: bool = False, fast: bool = False):
         L.orc_restore.argtypes = [C.c_void_p, C.c_int64] + [_dp] * 8 + [C.c_int64, _i32p, _i64p]
         L.orc_restore.restype = C.c_int
         L.orc_set_seed.argtypes = [C.c_void_p, C.c_uint64]
+        L.orc_set_jitter.argtypes = [C.c_void_p, C.c_uint64]
         _libs[path] = L
     return _libs[path]
 
@@ -131,7 +132,8 @@ class OracleSim:
     """One oracle simulation of a ``synth.Model``. ``batch_steps``: 0 inserts a spike's events at once; M > 0
     inserts them at the end of each M-step interval."""
 
-    def __init__(self, model, dt=None, batch_steps=0, n_threads=1, keep_matrix=False, fma=False, fast=False):
+    def __init__(self, model, dt=None, batch_steps=0, n_threads=1, keep_matrix=False, fma=False, fast=False,
+                 jitter=0):
         self.model = model
         self._L = lib(fma, fast)
         dt = float(model.dt if dt is None else dt)
@@ -195,6 +197,8 @@ class OracleSim:
         self._h = self._L.orc_create(C.byref(s))
         if not self._h:
             raise ValueError("oracle: " + self._L.orc_error().decode())
+        if jitter:
+            self._L.orc_set_jitter(self._h, int(jitter) & 0xFFFFFFFFFFFFFFFF)
 
     def __del__(self):
         h = getattr(self, "_h", None)

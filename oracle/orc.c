@@ -199,7 +199,23 @@ struct orc_model {
   int64_t n_delivered;
   int n_threads;
   char *spiked; double *spike_t;
+  uint64_t jitter; /* test hook: nonzero moves each potential by -1, 0 or +1 ulp after every step */
 };
+
+/* The rounding sensitivity probe behind orc_set_jitter: a counter-based choice of -1, 0 or +1 ulp for compartment i
+ * after step n (SplitMix64 finaliser of the three numbers), the size of the difference two correctly rounded
+ * implementations may have in any operation of a step. */
+static double jitter_ulp(double v, uint64_t seed, int64_t i, int64_t n) {
+  uint64_t z = seed ^ ((uint64_t)i * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)n * 0xD1B54A32D192ED03ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  switch ((z >> 32) % 3) {
+    case 0: return nextafter(v, -INFINITY);
+    case 1: return v;
+    default: return nextafter(v, INFINITY);
+  }
+}
 
 static void *xcalloc(size_t n, size_t s) { return calloc(n ? n : 1, s); }
 #define DUP(dst, src, n, T) do { (dst) = (T *)xcalloc((size_t)(n), sizeof(T)); if (!(dst)) goto nomem; \
@@ -546,6 +562,8 @@ static void cell_step(orc_model *m, int32_t cl, int64_t n) {
     for (int64_t i = i0; i < i0 + nn; ++i) m->last_dv[i] = rhs[i];
   double v_root_old = v[i0];
   for (int64_t i = i0; i < i0 + nn; ++i) v[i] += rhs[i];
+  if (m->jitter)
+    for (int64_t i = i0; i < i0 + nn; ++i) v[i] = jitter_ulp(v[i], m->jitter, i, n);
   /* state update with v_{n+1} (reading R1, R3, R5, R11) */
   for (int64_t q = m->hh_c.off[cl]; q < m->hh_c.off[cl + 1]; ++q) {
     int64_t k = m->hh_c.idx[q];
@@ -659,6 +677,8 @@ int orc_restore(orc_model *m, int64_t step, const double *v, const double *hh_m,
   m->step = step;
   return 0;
 }
+
+void orc_set_jitter(orc_model *m, uint64_t seed) { m->jitter = seed; }
 
 /* new key for the background streams from the current step on (a restart with other random streams) */
 void orc_set_seed(orc_model *m, uint64_t seed) { m->seed = seed; }

@@ -88,6 +88,13 @@ int orc_restore(orc_model *m, int64_t step, const double *v, const double *hh_m,
 /* key of the background streams from the current step on */
 void orc_set_seed(orc_model *m, uint64_t seed);
 
+/* Test hook, a rounding-sensitivity probe (not part of the method): with seed != 0, after every step each
+ * compartment's potential moves by -1, 0 or +1 ulp, chosen by a counter-based hash of (seed, compartment, step). Two
+ * FP64 implementations that evaluate the same step with different but correctly rounded operations differ by about
+ * this much per step; the spread this member shows is the deviation such an implementation may have from the oracle.
+ * 0 turns it off (the default). */
+void orc_set_jitter(orc_model *m, uint64_t seed);
+
 /* Test hooks.
  * Hines elimination of one tree of n nodes in place (Sec. 2; Sec. 4.4 on its operation count): on return rhs
  * holds the solution. Returns the number of floating-point operations performed. */

@@ -731,3 +731,32 @@ def test_restart_with_new_background_streams():
     with pytest.raises(RuntimeError):
         ok.run_to_step(1)
         ok.restore(ck)  # a model that has run
+
+
+def test_rounding_probe_moves_each_potential_by_at_most_one_ulp():
+    """the rounding-sensitivity probe (orc_set_jitter, test infrastructure for the GPU parity bar): off, it leaves the
+    oracle bitwise unchanged; on, one step moves each potential by -1, 0 or +1 ulp of the unperturbed result, with
+    all three outcomes present, independently of the thread count"""
+    m = synth.ring_network(n_cells=30, n_comp=20, seed=4)
+    plain = O.OracleSim(m)
+    off = O.OracleSim(m, jitter=0)
+    plain.run_to_step(40)
+    off.run_to_step(40)
+    assert np.array_equal(plain.v(), off.v())
+    base = O.OracleSim(m)
+    base.run_to_step(39)
+    ck = base.checkpoint()
+    ref = O.OracleSim(m)
+    ref.restore(ck)
+    ref.run_to_step(40)
+    outs = []
+    for threads in (1, 4):
+        j = O.OracleSim(m, n_threads=threads, jitter=12345)
+        j.restore(ck)
+        j.run_to_step(40)
+        outs.append(j.v())
+    assert np.array_equal(outs[0], outs[1])
+    v, r = outs[0], ref.v()
+    up, down = np.nextafter(r, np.inf), np.nextafter(r, -np.inf)
+    assert np.all((v == r) | (v == up) | (v == down))
+    assert np.any(v == up) and np.any(v == down) and np.any(v == r)
