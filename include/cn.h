@@ -163,6 +163,40 @@ int cn_voltages(const cn_model *m, double *v_out, int64_t n_comp);
  * HH 0:m 1:h 2:n; KM 0:n; CAHI 0:m 1:cai; EXPSYN 0:g. n must equal the instance count (else CN_E_INVALID). */
 int cn_mech_state(const cn_model *m, int32_t type, int32_t which, double *out, int64_t n);
 
+/* Checkpoint-restart (Sec. 3.4: a simulation saved at some step continues later, possibly with other stimuli or
+ * random streams). A checkpoint is what the readouts give at a step n: the step, cn_voltages, cn_mech_state of every
+ * state (the state update pending on the device is applied by that readout, so the states are those of step n) and
+ * the spikes so far (cn_spikes). Events still in flight at n are not stored: each is folded into the spike that sent
+ * it and rebuilt from the spike list on restore (every NetCon event of a listed spike due at or after step n is
+ * queued again). Arrays are in the caller's order and layout (as the readouts give them); a mechanism the model
+ * lacks takes NULL. */
+typedef struct cn_checkpoint {
+  int64_t step;                     /* the step n the state belongs to (t = n dt) */
+  const double *v;                  /* [n_comp] mV */
+  const double *hh_m, *hh_h, *hh_n; /* [instances of the HH table] */
+  const double *km_n;               /* [instances of the KM table] */
+  const double *cahi_m, *cahi_cai;  /* [instances of the CAHI table]; cai in mM */
+  const double *syn_g;              /* [ExpSyn instances] uS */
+  int64_t n_spikes;                 /* spikes with step <= n (older ones may be left out once their last event was
+                                       delivered) */
+  const int32_t *spike_gid;
+  const int64_t *spike_step;
+} cn_checkpoint;
+
+/* Continue a model from a checkpoint (Sec. 3.4). The model must not have run (fresh from cn_model_create, same
+ * description as the one checkpointed); the call fixes dt as a first cn_run would, writes potentials, states and
+ * conductances, rebuilds the in-flight events, and sets the current step to ck->step. A later cn_run continues
+ * exactly as the uninterrupted run would (bitwise, with the same seed). Spikes before the restart are not part of
+ * the restored model's spike list. Errors: CN_E_INVALID (missing or non-finite arrays, a spike after ck->step, a
+ * gid out of range), CN_E_STATE (the model has run, or dt differs from an earlier call), CN_E_CAPACITY (the rebuilt
+ * events overflow the event ring), CN_E_DEVICE. After a failure that reached the device the model refuses further
+ * runs (CN_E_STATE). */
+int cn_restore(cn_model *m, double dt, const cn_checkpoint *ck);
+
+/* Key of the per-synapse background streams (Sec. 3.5, counter-based Random123-type streams) from the current step
+ * on: a restart with other random streams. The draws of a step depend only on (key, stream id, step). */
+int cn_set_seed(cn_model *m, uint64_t seed);
+
 /* Model facts for reporting. */
 typedef struct cn_info {
   int64_t n_comp, n_syn, n_netcon, n_groups, step, device_bytes;

@@ -20,8 +20,10 @@ LIB_PATH = os.path.join(PKG, "libcn.so")
 CN_OK, CN_E_INVALID, CN_E_NOMEM, CN_E_DEVICE, CN_E_STATE, CN_E_CAPACITY, CN_E_NUMERIC = range(7)
 MECH_ID = {"hh": 0, "pas": 1, "km": 2, "cahi": 3, "expsyn": 4, "iclamp": 5}
 PRECISION = {"fp64": 0, "fp32_mech": 1}
-EXPORTS = ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_model_info", "cn_stats",
-           "cn_model_destroy", "cn_last_error")
+EXPORTS = ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_restore", "cn_set_seed",
+           "cn_model_info", "cn_stats", "cn_model_destroy", "cn_last_error")
+STATE_KEYS = (("hh", 0, "hh_m"), ("hh", 1, "hh_h"), ("hh", 2, "hh_n"), ("km", 0, "km_n"), ("cahi", 0, "cahi_m"),
+              ("cahi", 1, "cahi_cai"), ("expsyn", 0, "syn_g"))
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -49,6 +51,12 @@ class Network(C.Structure):
                 ("delay", _dp), ("threshold", _dp), ("threshold_scalar", C.c_double), ("n_kick", C.c_int64),
                 ("kick_step", _i64p), ("kick_syn", _i64p), ("kick_weight", _dp), ("poisson_rate_hz", C.c_double),
                 ("poisson_weight", _dp), ("seed", C.c_uint64), ("poisson_key", _i64p)]
+
+
+class Checkpoint(C.Structure):
+    _fields_ = [("step", C.c_int64), ("v", _dp), ("hh_m", _dp), ("hh_h", _dp), ("hh_n", _dp), ("km_n", _dp),
+                ("cahi_m", _dp), ("cahi_cai", _dp), ("syn_g", _dp), ("n_spikes", C.c_int64), ("spike_gid", _i32p),
+                ("spike_step", _i64p)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -95,12 +103,14 @@ def lib():
         L.cn_spikes.argtypes = [C.c_void_p, _i64p, _i32p, _i64p, _dp, C.c_int64]
         L.cn_voltages.argtypes = [C.c_void_p, _dp, C.c_int64]
         L.cn_mech_state.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_int64]
+        L.cn_restore.argtypes = [C.c_void_p, C.c_double, C.POINTER(Checkpoint)]
+        L.cn_set_seed.argtypes = [C.c_void_p, C.c_uint64]
         L.cn_model_info.argtypes = [C.c_void_p, C.POINTER(Info)]
         L.cn_stats.argtypes = [C.c_void_p, _dp, _i64p]
         L.cn_model_destroy.argtypes = [C.c_void_p]
         L.cn_model_destroy.restype = None
-        for f in ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_model_info",
-                  "cn_stats"):
+        for f in ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_restore",
+                  "cn_set_seed", "cn_model_info", "cn_stats"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -252,6 +262,37 @@ class Engine:
         out = np.empty(cnt)
         _check(lib().cn_mech_state(self._h, MECH_ID[mech], which, _ptr(out, C.c_double), cnt))
         return out
+
+    def checkpoint(self) -> dict:
+        """what a restart needs (cn_checkpoint): step, potentials, every mechanism state at this step, the spikes so far"""
+        gid, step, _ = self.spikes()
+        states = {key: (self.mech_state(mech, which) if mech in self.model.mechs else np.zeros(0))
+                  for mech, which, key in STATE_KEYS}
+        return dict(step=int(self.info()["step"]), v=self.voltages(), states=states, gid=gid, spike_step=step)
+
+    def restore(self, ck: dict):
+        """continue from a checkpoint (cn_restore); this engine must not have run"""
+        keep = []
+
+        def p(a, dt, ct):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return _ptr(a, ct)
+
+        st = ck["states"]
+        c = Checkpoint()
+        c.step = int(ck["step"])
+        c.v = p(ck["v"], np.float64, C.c_double)
+        for _, _, key in STATE_KEYS:
+            setattr(c, key, p(st[key], np.float64, C.c_double) if np.asarray(st[key]).size else _dp())
+        c.n_spikes = int(np.asarray(ck["gid"]).size)
+        c.spike_gid = p(ck["gid"], np.int32, C.c_int32)
+        c.spike_step = p(ck["spike_step"], np.int64, C.c_int64)
+        _check(lib().cn_restore(self._h, self.dt, C.byref(c)))
+
+    def set_seed(self, seed: int):
+        """key of the background streams from the current step on (cn_set_seed)"""
+        _check(lib().cn_set_seed(self._h, int(seed) & 0xFFFFFFFFFFFFFFFF))
 
     def info(self) -> dict:
         i = Info()

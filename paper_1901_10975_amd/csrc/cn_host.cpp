@@ -26,10 +26,13 @@ hipError_t set_interval_lds(bool fp32, int threads, int slots, bool uni, int lds
 int interval_row_bytes(int nmax);
 hipError_t launch_advance(int64_t *ctl, int32_t M, hipStream_t st);
 hipError_t launch_fanout(const KParams &p, hipStream_t st);
-hipError_t launch_set_ctl(int64_t *ctl, int64_t n_begin, int64_t n_target, hipStream_t st);
+hipError_t launch_set_ctl(int64_t *ctl, int64_t n_begin, int64_t n_target, int64_t n_fresh, uint64_t seed,
+                          hipStream_t st);
+hipError_t launch_insert_events(int32_t *ev_cnt, uint64_t *ev_key, int32_t cap, int64_t n, const int64_t *bucket,
+                                const uint64_t *key, int32_t *flags, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *ptr, int64_t n, int32_t v, hipStream_t st);
-hipError_t launch_read_state(const KParams &p, bool fp32, int64_t n_nodes, int64_t step, int type, int which,
-                             double *out, hipStream_t st);
+hipError_t launch_gather_state(const KParams &p, bool fp32, const int32_t *inst_dev, int64_t n, int64_t step,
+                               int64_t n_fresh, int type, int which, double *out, hipStream_t st);
 }  // namespace cn
 
 using namespace cn;
@@ -128,12 +131,17 @@ struct cn_model {
   std::vector<uint64_t> host_syn_key;
   std::vector<double> host_syn_e, host_syn_wbg;
   std::vector<int32_t> host_syn_q;
+  // network on the host, for rebuilding in-flight events at a restart: NetCons by source cell, target group and
+  // group-local synapse, delay in steps
+  std::vector<int64_t> host_out_off;
+  std::vector<int32_t> host_out_nc, host_tgt_g, host_tgt_l, host_D;
   int32_t max_levels = 0, max_group_syn = 0, max_group_nodes = 0, max_group_cells = 0;
 
   // ---- device
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<void *> allocs;
+  std::vector<size_t> alloc_bytes;
   int64_t device_bytes = 0;
   KParams kp{};
   int lds_bytes = 0;
@@ -146,6 +154,10 @@ struct cn_model {
   bool dt_fixed = false, broken = false;
   double dt = 0.0;
   int64_t step = 0;
+  int64_t fresh_step = 0;  // channel states on the device carry no pending update at this step (0, or a restart)
+  int device = 0;          // the HIP device of the model's stream
+  // per mechanism type, the device node (density mechanisms) or device synapse (ExpSyn) of each caller instance
+  const int32_t *inst_dev[CN_MECH_COUNT] = {};
   std::vector<int32_t> sp_gid;
   std::vector<int64_t> sp_step;
   std::vector<double> sp_t;
@@ -168,7 +180,20 @@ struct cn_model {
       if (e != hipSuccess) throw Err{CN_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
     }
     allocs.push_back(p);
+    alloc_bytes.push_back(bytes);
     return p;
+  }
+  // release one allocation of dalloc before the model ends (temporary buffers)
+  void dfree(void *p) {
+    for (size_t k = 0; k < allocs.size(); ++k) {
+      if (allocs[k] != p) continue;
+      device_bytes -= (int64_t)alloc_bytes[k];
+      allocs.erase(allocs.begin() + (long)k);
+      alloc_bytes.erase(alloc_bytes.begin() + (long)k);
+      if (opt.dev_alloc) opt.dev_free(p, opt.alloc_ctx);
+      else (void)hipFree(p);
+      return;
+    }
   }
   template <typename T>
   T *upload(const std::vector<T> &h) {
@@ -804,6 +829,10 @@ static void build_tables(cn_model *m) {
     for (int64_t k = 0; k < m->n_nc; ++k) onc[off[m->nc_src[k]] + fill[m->nc_src[k]]++] = (int32_t)k;
     p.out_off = m->upload(off);
     p.out_nc = m->upload(onc);
+    m->host_out_off = off;
+    m->host_out_nc = onc;
+    m->host_tgt_g = tgt_g;
+    m->host_tgt_l = tgt_l;
     std::vector<int64_t> kidx(m->n_kick);
     std::iota(kidx.begin(), kidx.end(), 0);
     std::vector<int32_t> kg(m->n_kick);
@@ -845,6 +874,30 @@ static void build_tables(cn_model *m) {
   }
   p.lvl_start = m->upload(m->lvl_start);
   p.n_groups = (int32_t)m->n_groups;
+  // readout tables: caller instance -> device node (density mechanisms with states; a dense table shares one) or
+  // device synapse (ExpSyn)
+  {
+    const int32_t *dense = nullptr;
+    for (int t : {CN_MECH_HH, CN_MECH_KM, CN_MECH_CAHI}) {
+      const Table &tb = m->mech[t];
+      if (!tb.present) continue;
+      bool is_dense = tb.n == N;
+      for (int64_t k = 0; is_dense && k < tb.n; ++k) is_dense = tb.node[k] == k;
+      if (is_dense && dense) {
+        m->inst_dev[t] = dense;
+        continue;
+      }
+      std::vector<int32_t> id(tb.n);
+      for (int64_t k = 0; k < tb.n; ++k) id[k] = (int32_t)m->dev_of_node[tb.node[k]];
+      m->inst_dev[t] = m->upload(id);
+      if (is_dense) dense = m->inst_dev[t];
+    }
+    if (syn.present) {
+      std::vector<int32_t> id(syn.n);
+      for (int64_t k = 0; k < syn.n; ++k) id[k] = (int32_t)m->dev_of_syn[k];
+      m->inst_dev[CN_MECH_EXPSYN] = m->upload(id);
+    }
+  }
 }
 
 // ---- tables that depend on dt; allocation of the event ring and spike buffers; graph capture
@@ -915,6 +968,7 @@ static void prepare_dt(cn_model *m, double dt) {
   p.M = (int32_t)M;
   p.ring = (int32_t)(2 + maxD / M);
   p.nc_D = m->upload(D);
+  m->host_D = D;
   // background stream threshold: event iff word < floor(p 2^32), p = rate dt 1e-3
   p.has_bg = m->rate > 0.0 ? 1 : 0;
   p.has_icl = m->mech[CN_MECH_ICLAMP].present && m->mech[CN_MECH_ICLAMP].n > 0 ? 1 : 0;
@@ -923,7 +977,6 @@ static void prepare_dt(cn_model *m, double dt) {
     const double t = std::floor(pr * 4294967296.0);
     p.bg_thresh = t >= 4294967296.0 ? 4294967296ull : (uint64_t)t;
   }
-  p.seed = m->seed;
   // event ring
   int cap = m->opt.event_capacity > 0 ? m->opt.event_capacity : 512;
   int pc = 1;
@@ -1045,6 +1098,55 @@ static void drain(cn_model *m, int32_t n_timed) {
   }
 }
 
+namespace cn {
+
+int set_error(int code, const char *msg) { return fail(code, msg); }
+
+int model_device(const cn_model *m) { return m->device; }
+
+// argument checks of the state readouts
+int mech_state_check(const cn_model *m, int32_t type, int32_t which, const double *out, int64_t n) {
+  if (!m || !out) return fail(CN_E_INVALID, "NULL argument");
+  if (m->dry) return fail(CN_E_STATE, "model was built with validate_only");
+  if (type < 0 || type >= CN_MECH_COUNT || !m->mech[type].present) return fail(CN_E_INVALID, "no such mechanism");
+  if (n != m->mech[type].n) return fail(CN_E_INVALID, "n does not match the instance count");
+  const int nw[CN_MECH_COUNT] = {3, 0, 1, 2, 1, 0};
+  if (which < 0 || which >= nw[type]) return fail(CN_E_INVALID, "no such state");
+  return CN_OK;
+}
+
+// A state readout after mech_state_check: one gather kernel writes the state of every instance, in the caller's
+// instance order, into the device buffer dbuf (n doubles; unused before the first run), which is then copied to out.
+// Allocates nothing itself.
+int mech_state_run(const cn_model *m, int32_t type, int32_t which, double *out, int64_t n, double *dbuf) {
+  if (n == 0) return CN_OK;
+  try {
+    if (!m->dt_fixed && type != CN_MECH_EXPSYN) {  // before the first run, states sit at their initial values
+      double hm, hh, hn;
+      hh_inf(m->v_init, hm, hh, hn);
+      double x = 0.0;
+      if (type == CN_MECH_HH) x = which == 0 ? hm : (which == 1 ? hh : hn);
+      else if (type == CN_MECH_KM) x = km_inf(m->v_init);
+      else x = which == 0 ? cahi_inf(m->v_init) : 5e-5;
+      for (int64_t k = 0; k < n; ++k) out[k] = m->fp32 ? (double)(float)x : x;
+      return CN_OK;
+    }
+    if (!m->dt_fixed) {  // no conductance before the first run
+      for (int64_t k = 0; k < n; ++k) out[k] = 0.0;
+      return CN_OK;
+    }
+    HIPCHK(launch_gather_state(m->kp, m->fp32, m->inst_dev[type], n, m->step, m->fresh_step, type, which, dbuf,
+                               m->stream));
+    HIPCHK(hipMemcpyAsync(out, dbuf, n * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+  } catch (const Err &e) {
+    return fail(e.code, e.msg);
+  }
+  return CN_OK;
+}
+
+}  // namespace cn
+
 extern "C" {
 
 const char *cn_last_error(void) { return g_err.c_str(); }
@@ -1068,6 +1170,7 @@ int cn_model_create(const cn_topology *topo, const cn_mech_table *mechs, int32_t
     if (m->opt.dev_alloc && !m->opt.dev_free) throw Err{CN_E_INVALID, "dev_alloc without dev_free"};
     m->fp32 = m->opt.precision == CN_PREC_FP32_MECH;
     if (topo->n_cells <= 0 || topo->n_comp <= 0) throw Err{CN_E_INVALID, "empty model"};
+    if (topo->n_comp >= (int64_t)INT32_MAX) throw Err{CN_E_INVALID, "more than 2^31 - 2 compartments"};
     if (!topo->cell_offset || !topo->parent || !topo->area || !topo->ri || !topo->cm)
       throw Err{CN_E_INVALID, "topology arrays missing"};
     if (!std::isfinite(topo->v_init) || !std::isfinite(topo->celsius)) throw Err{CN_E_INVALID, "non-finite v_init/celsius"};
@@ -1110,6 +1213,7 @@ int cn_model_create(const cn_topology *topo, const cn_mech_table *mechs, int32_t
       HIPCHK(hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking));
       m->own_stream = true;
     }
+    if (!m->dry) HIPCHK(hipGetDevice(&m->device));
     build_layout(m);
     build_tables(m);
     if (!m->dry) HIPCHK(hipStreamSynchronize(m->stream));
@@ -1150,7 +1254,7 @@ int cn_run(cn_model *m, double tstop, double dt) {
     if (N == m->step) return CN_OK;
     KParams &p = m->kp;
     touched = true;
-    HIPCHK(launch_set_ctl(p.ctl, m->step, N, m->stream));
+    HIPCHK(launch_set_ctl(p.ctl, m->step, N, m->fresh_step, m->seed, m->stream));
     const bool timing = m->opt.timing != 0;
     if (timing && (int32_t)m->ev_pool.size() < 2 * m->drain_every) {
       while ((int32_t)m->ev_pool.size() < 2 * m->drain_every) {
@@ -1228,51 +1332,136 @@ int cn_voltages(const cn_model *m, double *v_out, int64_t n_comp) {
 }
 
 int cn_mech_state(const cn_model *m, int32_t type, int32_t which, double *out, int64_t n) {
-  if (!m || !out) return fail(CN_E_INVALID, "NULL argument");
-  if (m->dry) return fail(CN_E_STATE, "model was built with validate_only");
-  if (type < 0 || type >= CN_MECH_COUNT || !m->mech[type].present) return fail(CN_E_INVALID, "no such mechanism");
-  const Table &tb = m->mech[type];
-  if (n != tb.n) return fail(CN_E_INVALID, "n does not match the instance count");
-  const int nw[CN_MECH_COUNT] = {3, 0, 1, 2, 1, 0};
-  if (which < 0 || which >= nw[type]) return fail(CN_E_INVALID, "no such state");
-  try {
-    HIPCHK(hipStreamSynchronize(m->stream));
-    if (type == CN_MECH_EXPSYN) {
-      std::vector<double> g(tb.n);
-      if (m->fp32) {
-        std::vector<float> f(tb.n);
-        HIPCHK(hipMemcpy(f.data(), m->kp.syn_g, tb.n * sizeof(float), hipMemcpyDeviceToHost));
-        for (int64_t d = 0; d < tb.n; ++d) g[d] = f[d];
-      } else {
-        HIPCHK(hipMemcpy(g.data(), m->kp.syn_g, tb.n * sizeof(double), hipMemcpyDeviceToHost));
-      }
-      for (int64_t k = 0; k < tb.n; ++k) out[k] = g[m->dev_of_syn[k]];
-      return CN_OK;
-    }
-    if (!m->dt_fixed) {  // before the first run states sit at their initial values
-      double hm, hh, hn;
-      hh_inf(m->v_init, hm, hh, hn);
-      for (int64_t k = 0; k < tb.n; ++k) {
-        double x = 0.0;
-        if (type == CN_MECH_HH) x = which == 0 ? hm : (which == 1 ? hh : hn);
-        else if (type == CN_MECH_KM) x = km_inf(m->v_init);
-        else x = which == 0 ? cahi_inf(m->v_init) : 5e-5;
-        out[k] = m->fp32 ? (double)(float)x : x;
-      }
-      return CN_OK;
-    }
-    double *buf = nullptr;
-    HIPCHK(hipMalloc(&buf, std::max<int64_t>(1, m->n_comp) * sizeof(double)));
-    std::vector<double> h(m->n_comp);
-    hipError_t e = launch_read_state(m->kp, m->fp32, m->n_comp, m->step, type, which, buf, m->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
-    if (e == hipSuccess) e = hipMemcpy(h.data(), buf, m->n_comp * sizeof(double), hipMemcpyDeviceToHost);
-    (void)hipFree(buf);
-    HIPCHK(e);
-    for (int64_t k = 0; k < tb.n; ++k) out[k] = h[m->dev_of_node[tb.node[k]]];
-  } catch (const Err &e) {
-    return fail(e.code, e.msg);
+  const int rc = mech_state_check(m, type, which, out, n);
+  if (rc != CN_OK) return rc;
+  double *buf = nullptr;
+  if (m->dt_fixed && n > 0) {
+    const hipError_t e = hipMalloc(&buf, n * sizeof(double));
+    if (e != hipSuccess) return fail(CN_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
+  const int r = mech_state_run(m, type, which, out, n, buf);
+  if (buf) (void)hipFree(buf);
+  return r;
+}
+
+int cn_restore(cn_model *m, double dt, const cn_checkpoint *ck) {
+  if (!m || !ck) return fail(CN_E_INVALID, "NULL argument");
+  if (m->broken) return fail(CN_E_STATE, "model is in an error state after a failed run");
+  if (m->dry) return fail(CN_E_STATE, "model was built with validate_only");
+  if (m->step != 0 || !m->sp_gid.empty()) return fail(CN_E_STATE, "restore needs a model that has not run");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CN_E_INVALID, "bad dt");
+  if (m->dt_fixed && dt != m->dt) return fail(CN_E_STATE, "dt differs from the first cn_run call");
+  if (ck->step < 0) return fail(CN_E_INVALID, "negative restart step");
+  if (!ck->v || !finite_all(ck->v, m->n_comp)) return fail(CN_E_INVALID, "checkpoint potentials missing or non-finite");
+  const Table &hh = m->mech[CN_MECH_HH], &km = m->mech[CN_MECH_KM], &ca = m->mech[CN_MECH_CAHI],
+              &syn = m->mech[CN_MECH_EXPSYN];
+  auto need = [&](const Table &t, const double *x) { return !t.present || t.n == 0 || (x && finite_all(x, t.n)); };
+  if (!need(hh, ck->hh_m) || !need(hh, ck->hh_h) || !need(hh, ck->hh_n) || !need(km, ck->km_n) ||
+      !need(ca, ck->cahi_m) || !need(ca, ck->cahi_cai) || !need(syn, ck->syn_g))
+    return fail(CN_E_INVALID, "checkpoint state of a present mechanism missing or non-finite");
+  if (ck->n_spikes < 0 || (ck->n_spikes > 0 && (!ck->spike_gid || !ck->spike_step)))
+    return fail(CN_E_INVALID, "checkpoint spike arrays missing");
+  for (int64_t q = 0; q < ck->n_spikes; ++q)
+    if (ck->spike_gid[q] < 0 || ck->spike_gid[q] >= m->n_cells || ck->spike_step[q] < 0 ||
+        ck->spike_step[q] > ck->step)
+      return fail(CN_E_INVALID, "checkpoint spike " + std::to_string(q) + " out of range");
+  bool touched = false;
+  void *tmp_b = nullptr, *tmp_k = nullptr;
+  try {
+    if (!m->dt_fixed) {
+      touched = true;
+      prepare_dt(m, dt);
+      m->dt = dt;
+      m->dt_fixed = true;
+    }
+    touched = true;
+    KParams &p = m->kp;
+    const int64_t N = m->n_comp;
+    HIPCHK(hipStreamSynchronize(m->stream));
+    {
+      std::vector<double> dv(N);
+      for (int64_t i = 0; i < N; ++i) dv[m->dev_of_node[i]] = ck->v[i];
+      HIPCHK(hipMemcpy(p.v, dv.data(), N * sizeof(double), hipMemcpyHostToDevice));
+    }
+    // channel states: the device copy (initial values where a mechanism is absent) with the checkpoint's values
+    // written over it; the states are fresh at the restart step (no pending update)
+    auto put_states = [&](auto zero) {
+      using S = decltype(zero);
+      std::vector<StRec<S>> r(N);
+      HIPCHK(hipMemcpy(r.data(), p.st, N * sizeof(StRec<S>), hipMemcpyDeviceToHost));
+      for (int64_t k = 0; k < hh.n && hh.present; ++k) {
+        StRec<S> &x = r[m->dev_of_node[hh.node[k]]];
+        x.m = (S)ck->hh_m[k];
+        x.h = (S)ck->hh_h[k];
+        x.n = (S)ck->hh_n[k];
+      }
+      for (int64_t k = 0; k < km.n && km.present; ++k) r[m->dev_of_node[km.node[k]]].kn = (S)ck->km_n[k];
+      for (int64_t k = 0; k < ca.n && ca.present; ++k) {
+        StRec<S> &x = r[m->dev_of_node[ca.node[k]]];
+        x.cm = (S)ck->cahi_m[k];
+        x.cai = (S)ck->cahi_cai[k];
+      }
+      HIPCHK(hipMemcpy(p.st, r.data(), N * sizeof(StRec<S>), hipMemcpyHostToDevice));
+      std::vector<S> g(syn.n);
+      for (int64_t k = 0; k < syn.n; ++k) g[m->dev_of_syn[k]] = (S)ck->syn_g[k];
+      if (syn.n) HIPCHK(hipMemcpy(p.syn_g, g.data(), syn.n * sizeof(S), hipMemcpyHostToDevice));
+    };
+    if (m->fp32) put_states(0.0f);
+    else put_states(0.0);
+    // events still in flight at the restart step, rebuilt from the spikes that sent them: every NetCon event due at
+    // or after the step goes to the ring bucket of its interval and target group
+    const int64_t s = ck->step, M = p.M, ival = s / M;
+    std::vector<int64_t> bucket;
+    std::vector<uint64_t> key;
+    for (int64_t q = 0; q < ck->n_spikes; ++q) {
+      const int32_t gid = ck->spike_gid[q];
+      for (int64_t o = m->host_out_off[gid]; o < m->host_out_off[gid + 1]; ++o) {
+        const int32_t nc = m->host_out_nc[o];
+        const int64_t due = ck->spike_step[q] + m->host_D[nc];
+        if (due < s) continue;  // delivered before the checkpoint
+        const int64_t it = due / M;
+        if (it - ival >= p.ring) throw Err{CN_E_INVALID, "checkpoint spike beyond the event horizon"};
+        const uint64_t k = ((uint64_t)(due - it * M) << EV_STEP_SHIFT) |
+                           ((uint64_t)(uint32_t)m->host_tgt_l[nc] << EV_SYN_SHIFT) | EV_KIND_NETCON | (uint32_t)nc;
+        bucket.push_back((it % p.ring) * m->n_groups + m->host_tgt_g[nc]);
+        key.push_back(k);
+      }
+    }
+    HIPCHK(launch_fill_i32(p.ev_cnt, (int64_t)p.ring * m->n_groups, 0, m->stream));
+    HIPCHK(launch_fill_i32(p.flags, 4, 0, m->stream));
+    if (!key.empty()) {
+      tmp_b = m->dalloc(bucket.size() * sizeof(int64_t));
+      tmp_k = m->dalloc(key.size() * sizeof(uint64_t));
+      HIPCHK(hipMemcpyAsync(tmp_b, bucket.data(), bucket.size() * sizeof(int64_t), hipMemcpyHostToDevice, m->stream));
+      HIPCHK(hipMemcpyAsync(tmp_k, key.data(), key.size() * sizeof(uint64_t), hipMemcpyHostToDevice, m->stream));
+      HIPCHK(launch_insert_events(p.ev_cnt, p.ev_key, p.ev_cap, (int64_t)key.size(), static_cast<int64_t *>(tmp_b),
+                                  static_cast<uint64_t *>(tmp_k), p.flags, m->stream));
+    }
+    HIPCHK(hipStreamSynchronize(m->stream));
+    if (tmp_b) m->dfree(tmp_b);
+    if (tmp_k) m->dfree(tmp_k);
+    tmp_b = tmp_k = nullptr;
+    int32_t flags[4];
+    HIPCHK(hipMemcpy(flags, p.flags, sizeof flags, hipMemcpyDeviceToHost));
+    if (flags[FLAG_EV_OVERFLOW]) throw Err{CN_E_CAPACITY, "event ring overflow: raise cn_options.event_capacity"};
+    m->step = s;
+    m->fresh_step = s;
+  } catch (const Err &e) {
+    if (touched) m->broken = true;
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc &) {
+    if (touched) m->broken = true;
+    return fail(CN_E_NOMEM, "out of host memory");
+  } catch (...) {
+    if (touched) m->broken = true;
+    return fail(CN_E_DEVICE, "unexpected failure in cn_restore");
+  }
+  return CN_OK;
+}
+
+int cn_set_seed(cn_model *m, uint64_t seed) {
+  if (!m) return fail(CN_E_INVALID, "model is NULL");
+  m->seed = seed;
   return CN_OK;
 }
 

@@ -129,11 +129,11 @@ struct KParams {
   double *rec_t;
   int32_t rec_cap;
   int32_t *flags;          // [0] event overflow, [1] spike record overflow, [2] non-finite voltage
-  int64_t *ctl;            // [0] first step of the next chunk, [1] target step
+  int64_t *ctl;            // [0] first step of the next chunk, [1] target step, [2] the step whose channel states
+                           // carry no pending update (0, or the step of a restart), [3] key of the background streams
   // constants
   double dt, q10dt;
   double ca_fm, ca_fr, ca_k;  // cahi: 1-exp(-dt/tau_m), 1-exp(-dt/tau_r), 1e4 tau_r / (2 F depth)
-  uint64_t seed;
   uint64_t bg_thresh;
 };
 

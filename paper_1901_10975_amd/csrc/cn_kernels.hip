@@ -282,6 +282,8 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
   const GroupDesc gd = p.groups[G];
   const int64_t n_begin = p.ctl[0];
   const int64_t n_target = p.ctl[1];
+  const int64_t n_fresh = p.ctl[2];  // the step whose channel states carry no pending update (0, or a restart)
+  const uint64_t seed = (uint64_t)p.ctl[3];
   const int M = p.M;
   const int64_t ival = n_begin / M;
   const int64_t n_end = min(n_target, (ival + 1) * (int64_t)M);
@@ -454,7 +456,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     // background-event bits for a block of four steps (one Philox call gives four words)
     if (p.has_bg && (n == n_begin || (n & 3) == 0)) {
       const uint64_t blk = (uint64_t)n >> 2;
-      for (int i = tid0; i < n_syn; i += stride) bgm[i] = (uint8_t)bg_mask4(p.seed, syn[i].key, blk, p.bg_thresh);
+      for (int i = tid0; i < n_syn; i += stride) bgm[i] = (uint8_t)bg_mask4(seed, syn[i].key, blk, p.bg_thresh);
     }
     // A: delivery (Sec. 2, event-driven delivery step): one thread per synapse run, in key order
     const int sn = (int)(n - ival * M);
@@ -527,7 +529,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     // ---- C: states, currents, conductances and the compartment's own axial terms. Throughput work: it runs at
     // the lower wave priority, so that a co-resident group's latency-bound sweeps issue ahead of it.
     __builtin_amdgcn_s_setprio(0);
-    const bool pend = n > 0;
+    const bool pend = n > n_fresh;
     const S q10dt = (S)(KARG ? p.q10dt : cst[C_Q10DT]);
     const S sdt = (S)(KARG ? p.dt : cst[C_DT]);
     const S ca_fm = (S)(KARG ? p.ca_fm : cst[C_CA_FM]), ca_fr = (S)(KARG ? p.ca_fr : cst[C_CA_FR]),
@@ -835,10 +837,25 @@ __global__ void cn_advance(int64_t *ctl, int32_t M) {
   }
 }
 
-__global__ void cn_set_ctl(int64_t *ctl, int64_t n_begin, int64_t n_target) {
+// control block of a run: first step, target step, the step whose states are fresh, background key
+__global__ void cn_set_ctl(int64_t *ctl, int64_t n_begin, int64_t n_target, int64_t n_fresh, uint64_t seed) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctl[0] = n_begin;
     ctl[1] = n_target;
+    ctl[2] = n_fresh;
+    ctl[3] = (int64_t)seed;
+  }
+}
+
+// events rebuilt by a restart: key k goes to ring bucket bucket[k] (the interval kernel sorts each bucket's keys, so
+// the order of arrival does not matter)
+__global__ void cn_insert_events(int32_t *ev_cnt, uint64_t *ev_key, int32_t cap, int64_t n, const int64_t *bucket,
+                                 const uint64_t *key, int32_t *flags) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = bucket[i];
+    const int pos = atomicAdd(&ev_cnt[b], 1);
+    if (pos < cap) ev_key[b * cap + pos] = key[i];
+    else atomicOr(&flags[FLAG_EV_OVERFLOW], 1);
   }
 }
 
@@ -847,30 +864,36 @@ __global__ void cn_fill_i32(int32_t *p, int64_t n, int32_t v) {
     p[i] = v;
 }
 
-// mechanism state readout at the current step: states are stored one update behind (the update of the last step
-// is applied at the start of the next), so apply it to a copy here.
+// Mechanism state readout at the current step, in the caller's instance order: instance k sits at device node (or,
+// for ExpSyn, device synapse) inst_dev[k]. Channel states are stored one update behind (the update of the last step is
+// applied at the start of the next), so the pending update is applied to a copy here.
 template <typename S>
-__global__ void cn_read_state(const KParams p, int64_t n_nodes, int64_t step, int type, int which, double *out) {
+__global__ void cn_gather_state(const KParams p, const int32_t *inst_dev, int64_t n, int64_t step, int64_t n_fresh,
+                                int type, int which, double *out) {
   __shared__ double tab[64];
   if (threadIdx.x < 64) tab[threadIdx.x] = p.exp_tab[threadIdx.x];
   __syncthreads();
   const lds_table *et = (const lds_table *)tab;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n_nodes) return;
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t i = inst_dev[k];
+  if (type == 4) {
+    out[k] = (double)static_cast<const S *>(p.syn_g)[i];
+    return;
+  }
   const double v = p.v[i];
-  const bool pend = step > 0;
+  const bool pend = step > n_fresh;
   StRec<S> sr = static_cast<const StRec<S> *>(p.st)[i];
-  const int64_t sst = p.n_nodes_total;
   if (type == 0) {
     if (pend) hh_advance<S>(v, (S)p.q10dt, sr.m, sr.h, sr.n, et);
-    out[i] = which == 0 ? (double)sr.m : (which == 1 ? (double)sr.h : (double)sr.n);
+    out[k] = which == 0 ? (double)sr.m : (which == 1 ? (double)sr.h : (double)sr.n);
   } else if (type == 2) {
     if (pend) km_advance<S>(v, (S)p.dt, sr.kn, et);
-    out[i] = (double)sr.kn;
+    out[k] = (double)sr.kn;
   } else if (type == 3) {
-    const S gca = (S)(p.prm ? p.prm[P_CA_G * sst + i] : p.prm_s[P_CA_G]);
+    const S gca = (S)(p.prm ? p.prm[P_CA_G * p.n_nodes_total + i] : p.prm_s[P_CA_G]);
     if (pend) cahi_advance<S>(v, (S)p.ca_fm, (S)p.ca_fr, (S)p.ca_k, gca, sr.cm, sr.cai, et);
-    out[i] = which == 0 ? (double)sr.cm : (double)sr.cai;
+    out[k] = which == 0 ? (double)sr.cm : (double)sr.cai;
   }
 }
 
@@ -936,8 +959,19 @@ hipError_t launch_advance(int64_t *ctl, int32_t M, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_set_ctl(int64_t *ctl, int64_t n_begin, int64_t n_target, hipStream_t st) {
-  hipLaunchKernelGGL(cn_set_ctl, dim3(1), dim3(64), 0, st, ctl, n_begin, n_target);
+hipError_t launch_set_ctl(int64_t *ctl, int64_t n_begin, int64_t n_target, int64_t n_fresh, uint64_t seed,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(cn_set_ctl, dim3(1), dim3(64), 0, st, ctl, n_begin, n_target, n_fresh, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_insert_events(int32_t *ev_cnt, uint64_t *ev_key, int32_t cap, int64_t n, const int64_t *bucket,
+                                const uint64_t *key, int32_t *flags, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(cn_insert_events, dim3((unsigned)blocks), dim3(256), 0, st, ev_cnt, ev_key, cap, n, bucket, key,
+                     flags);
   return hipGetLastError();
 }
 
@@ -949,12 +983,16 @@ hipError_t launch_fill_i32(int32_t *ptr, int64_t n, int32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_read_state(const KParams &p, bool fp32, int64_t n_nodes, int64_t step, int type, int which,
-                             double *out, hipStream_t st) {
-  if (n_nodes <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((n_nodes + 255) / 256);
-  if (fp32) hipLaunchKernelGGL(cn_read_state<float>, dim3(blocks), dim3(256), 0, st, p, n_nodes, step, type, which, out);
-  else hipLaunchKernelGGL(cn_read_state<double>, dim3(blocks), dim3(256), 0, st, p, n_nodes, step, type, which, out);
+hipError_t launch_gather_state(const KParams &p, bool fp32, const int32_t *inst_dev, int64_t n, int64_t step,
+                               int64_t n_fresh, int type, int which, double *out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (fp32)
+    hipLaunchKernelGGL(cn_gather_state<float>, dim3(blocks), dim3(256), 0, st, p, inst_dev, n, step, n_fresh, type,
+                       which, out);
+  else
+    hipLaunchKernelGGL(cn_gather_state<double>, dim3(blocks), dim3(256), 0, st, p, inst_dev, n, step, n_fresh, type,
+                       which, out);
   return hipGetLastError();
 }
 

@@ -114,3 +114,16 @@ def test_host_layout_checks_pass(name):
     with pytest.raises(cn.CnError) as err:
         e.run(1.0)
     assert err.value.code == cn.CN_E_STATE
+
+
+def test_restore_and_seed_argument_checks():
+    """checkpoint-restart entry points reject NULL arguments and models without a device, before any device work"""
+    L = cn.lib()
+    assert L.cn_restore(None, 0.025, None) == cn.CN_E_INVALID
+    assert L.cn_set_seed(None, 1) == cn.CN_E_INVALID
+    e = cn.Engine(_tiny(), use_torch=False, validate_only=True)
+    ck = dict(step=40, v=np.full(6, -65.0), states={k: np.zeros(0) for _, _, k in cn.STATE_KEYS},
+              gid=np.zeros(0, np.int32), spike_step=np.zeros(0, np.int64))
+    with pytest.raises(cn.CnError) as err:
+        e.restore(ck)
+    assert err.value.code == cn.CN_E_STATE
