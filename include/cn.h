@@ -131,7 +131,11 @@ typedef struct cn_options {
   int32_t fault_inject;   /* tests of the error paths only (0 in normal use): 1 makes the first spike-record drain of
                              cn_run report a device failure after real work was queued; 2 makes the graph capture
                              fail after it began */
-  int32_t reserved[5];
+  int32_t group_slots;    /* compartments per thread in a cell group (0: auto); with group_threads it sets the group
+                             capacity group_threads * group_slots (shapes compiled: 128 x 2/4/8, 256 x 1/2/4,
+                             512 x 2/4/8), as cn_autotune chooses it */
+  int32_t group_fill_pct; /* cells are packed into a group up to this percentage of its capacity (0: 100) */
+  int32_t reserved[3];
 } cn_options;
 
 typedef struct cn_model cn_model;
@@ -196,6 +200,35 @@ int cn_restore(cn_model *m, double dt, const cn_checkpoint *ck);
 /* Key of the per-synapse background streams (Sec. 3.5, counter-based Random123-type streams) from the current step
  * on: a restart with other random streams. The draws of a step depend only on (key, stream id, step). */
 int cn_set_seed(cn_model *m, uint64_t seed);
+
+/* Autotuner of the cell-group shape (Sec. 4.1: cells are grouped so that groups have equal cost; here the group is
+ * what one workgroup advances through a minimum-delay interval). Candidate shapes (threads x compartments per thread,
+ * and a packing fill) that hold the largest cell are each built as a model from the same description and options,
+ * run for one warm-up interval and then timed over five intervals with HIP events on the model's stream; the shape
+ * with the lowest median interval time wins. Results are cached in the process by a signature of the model
+ * (cell-size histogram, synapse and mechanism counts, precision, dt, interval and capacity options): a second call
+ * with the same signature returns the cached choice without timing. budget_ms bounds the wall time spent timing
+ * (at least the default shape and one other are always timed). The caller then creates its model with
+ * opt.group_threads, opt.group_slots and opt.group_fill_pct set from the result. The shape changes only the
+ * grouping, never the arithmetic of a compartment, so a tuned model's results equal the default model's bitwise.
+ * Arguments as for cn_model_create (borrowed); opt->group_threads/group_slots/group_fill_pct are ignored. Errors:
+ * those of cn_model_create and cn_run for the default shape (a failing non-default candidate is skipped). */
+#define CN_TUNE_MAX_CANDIDATES 16
+typedef struct cn_tune_result {
+  int32_t group_threads, group_slots, group_fill_pct; /* the chosen shape */
+  int32_t default_threads, default_slots;              /* the shape of the default rule */
+  int32_t n_candidates;                                /* shapes timed by this call (0 when taken from the cache) */
+  int32_t from_cache;
+  int32_t pad;
+  double interval_ms;                                  /* median interval time of the chosen shape */
+  double default_ms;                                   /* median interval time of the default shape */
+  uint64_t signature;
+  int32_t cand_threads[CN_TUNE_MAX_CANDIDATES], cand_slots[CN_TUNE_MAX_CANDIDATES],
+      cand_fill[CN_TUNE_MAX_CANDIDATES];
+  double cand_ms[CN_TUNE_MAX_CANDIDATES];
+} cn_tune_result;
+int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
+                const cn_options *opt, double dt, double budget_ms, cn_tune_result *out);
 
 /* Model facts for reporting. */
 typedef struct cn_info {

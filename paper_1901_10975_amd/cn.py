@@ -21,7 +21,7 @@ CN_OK, CN_E_INVALID, CN_E_NOMEM, CN_E_DEVICE, CN_E_STATE, CN_E_CAPACITY, CN_E_NU
 MECH_ID = {"hh": 0, "pas": 1, "km": 2, "cahi": 3, "expsyn": 4, "iclamp": 5}
 PRECISION = {"fp64": 0, "fp32_mech": 1}
 EXPORTS = ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_restore", "cn_set_seed",
-           "cn_model_info", "cn_stats", "cn_model_destroy", "cn_last_error")
+           "cn_autotune", "cn_model_info", "cn_stats", "cn_model_destroy", "cn_last_error")
 STATE_KEYS = (("hh", 0, "hh_m"), ("hh", 1, "hh_h"), ("hh", 2, "hh_n"), ("km", 0, "km_n"), ("cahi", 0, "cahi_m"),
               ("cahi", 1, "cahi_cai"), ("expsyn", 0, "syn_g"))
 
@@ -68,7 +68,19 @@ class Options(C.Structure):
                 ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p), ("event_capacity", C.c_int32),
                 ("max_interval", C.c_int32), ("group_threads", C.c_int32), ("use_graph", C.c_int32),
                 ("timing", C.c_int32), ("validate_only", C.c_int32), ("fault_inject", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("group_slots", C.c_int32), ("group_fill_pct", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+TUNE_MAX = 16
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("group_threads", C.c_int32), ("group_slots", C.c_int32), ("group_fill_pct", C.c_int32),
+                ("default_threads", C.c_int32), ("default_slots", C.c_int32), ("n_candidates", C.c_int32),
+                ("from_cache", C.c_int32), ("pad", C.c_int32), ("interval_ms", C.c_double),
+                ("default_ms", C.c_double), ("signature", C.c_uint64), ("cand_threads", C.c_int32 * TUNE_MAX),
+                ("cand_slots", C.c_int32 * TUNE_MAX), ("cand_fill", C.c_int32 * TUNE_MAX),
+                ("cand_ms", C.c_double * TUNE_MAX)]
 
 
 class Info(C.Structure):
@@ -105,12 +117,14 @@ def lib():
         L.cn_mech_state.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_int64]
         L.cn_restore.argtypes = [C.c_void_p, C.c_double, C.POINTER(Checkpoint)]
         L.cn_set_seed.argtypes = [C.c_void_p, C.c_uint64]
+        L.cn_autotune.argtypes = [C.POINTER(Topology), C.POINTER(MechTable), C.c_int32, C.POINTER(Network),
+                                  C.POINTER(Options), C.c_double, C.c_double, C.POINTER(TuneResult)]
         L.cn_model_info.argtypes = [C.c_void_p, C.POINTER(Info)]
         L.cn_stats.argtypes = [C.c_void_p, _dp, _i64p]
         L.cn_model_destroy.argtypes = [C.c_void_p]
         L.cn_model_destroy.restype = None
         for f in ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_restore",
-                  "cn_set_seed", "cn_model_info", "cn_stats"):
+                  "cn_set_seed", "cn_autotune", "cn_model_info", "cn_stats"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -149,59 +163,81 @@ class _TorchMemory:
         self.live.pop(int(ptr or 0), None)
 
 
+def _describe(model: "synth.Model", keep: list):
+    """the model description of cn_model_create (topology, mechanism tables, network) as ctypes structures; arrays
+    are appended to `keep`, which the caller holds for the duration of the call"""
+
+    def arr(x, dtype):
+        a = np.ascontiguousarray(np.asarray(x), dtype=dtype)
+        keep.append(a)
+        return a
+
+    n = model.n_comp
+    topo = Topology(model.n_cells, n, _ptr(arr(model.cell_offset, np.int64), C.c_int64),
+                    _ptr(arr(model.parent, np.int32), C.c_int32), _ptr(arr(model.area, np.float64), C.c_double),
+                    _ptr(arr(model.ri, np.float64), C.c_double), _ptr(arr(model.cm, np.float64), C.c_double),
+                    model.v_init, model.celsius)
+    tables = []
+    for name, t in model.mechs.items():
+        mt = MechTable()
+        mt.type = MECH_ID[name]
+        mt.n = t.count(n)
+        mt.node = _ptr(arr(t.node, np.int64), C.c_int64) if t.node is not None else _i64p()
+        for j, pname in enumerate(synth.MECH_PARAMS[name]):
+            v = t.params[pname]
+            if np.isscalar(v):
+                mt.param[j] = _dp()
+                mt.param_scalar[j] = float(v)
+            else:
+                mt.param[j] = _ptr(arr(v, np.float64), C.c_double)
+        tables.append(mt)
+    mtab = (MechTable * max(1, len(tables)))(*tables)
+    keep.append(mtab)
+    pw = model.poisson_weight if model.poisson_weight.shape[0] else None
+    net = Network(model.nc_src.shape[0], _ptr(arr(model.nc_src, np.int32), C.c_int32),
+                  _ptr(arr(model.nc_syn, np.int64), C.c_int64), _ptr(arr(model.nc_weight, np.float64), C.c_double),
+                  _ptr(arr(model.nc_delay, np.float64), C.c_double),
+                  _ptr(arr(model.threshold, np.float64), C.c_double), 0.0, model.kick_step.shape[0],
+                  _ptr(arr(model.kick_step, np.int64), C.c_int64), _ptr(arr(model.kick_syn, np.int64), C.c_int64),
+                  _ptr(arr(model.kick_weight, np.float64), C.c_double), float(model.poisson_rate_hz),
+                  _ptr(arr(pw, np.float64), C.c_double) if pw is not None else _dp(),
+                  int(model.seed) & 0xFFFFFFFFFFFFFFFF,
+                  _ptr(arr(model.poisson_key, np.int64), C.c_int64) if model.poisson_key is not None
+                  else _i64p())
+    return topo, mtab, len(tables), net
+
+
+def _tune_dict(r: TuneResult) -> dict:
+    k = r.n_candidates
+    return {"group_threads": r.group_threads, "group_slots": r.group_slots, "group_fill_pct": r.group_fill_pct,
+            "interval_ms": r.interval_ms, "default_threads": r.default_threads, "default_slots": r.default_slots,
+            "default_ms": r.default_ms, "from_cache": bool(r.from_cache), "signature": f"{r.signature:016x}",
+            "candidates": [{"threads": r.cand_threads[i], "slots": r.cand_slots[i], "fill_pct": r.cand_fill[i],
+                            "interval_ms": r.cand_ms[i]} for i in range(k)]}
+
+
 class Engine:
-    """A cn model on the GPU, built from a ``synth.Model``."""
+    """A cn model on the GPU, built from a ``synth.Model``. ``autotune``: choose the cell-group shape with
+    cn_autotune first (timed on this model's description; cached in the library by the model's signature), with a
+    wall-time budget of ``tune_budget_ms``; the choice is kept in ``self.tune``."""
 
     def __init__(self, model: "synth.Model", precision: str = "fp64", use_graph: bool = True, timing: bool = False,
-                 event_capacity: int = 0, max_interval: int = 0, group_threads: int = 0, use_torch: bool = True,
-                 stream=None, validate_only: bool = False, fault_inject: int = 0):
+                 event_capacity: int = 0, max_interval: int = 0, group_threads: int = 0, group_slots: int = 0,
+                 group_fill_pct: int = 0, use_torch: bool = True, stream=None, validate_only: bool = False,
+                 fault_inject: int = 0, autotune: bool = False, tune_budget_ms: float = 60000.0):
         L = lib()
         self.model = model
         self.dt = float(model.dt)
         keep = []
-
-        def arr(x, dtype):
-            a = np.ascontiguousarray(np.asarray(x), dtype=dtype)
-            keep.append(a)
-            return a
-
-        n = model.n_comp
-        topo = Topology(model.n_cells, n, _ptr(arr(model.cell_offset, np.int64), C.c_int64),
-                        _ptr(arr(model.parent, np.int32), C.c_int32), _ptr(arr(model.area, np.float64), C.c_double),
-                        _ptr(arr(model.ri, np.float64), C.c_double), _ptr(arr(model.cm, np.float64), C.c_double),
-                        model.v_init, model.celsius)
-        tables = []
-        for name, t in model.mechs.items():
-            mt = MechTable()
-            mt.type = MECH_ID[name]
-            mt.n = t.count(n)
-            mt.node = _ptr(arr(t.node, np.int64), C.c_int64) if t.node is not None else _i64p()
-            for j, pname in enumerate(synth.MECH_PARAMS[name]):
-                v = t.params[pname]
-                if np.isscalar(v):
-                    mt.param[j] = _dp()
-                    mt.param_scalar[j] = float(v)
-                else:
-                    mt.param[j] = _ptr(arr(v, np.float64), C.c_double)
-            tables.append(mt)
-        mtab = (MechTable * max(1, len(tables)))(*tables)
-        pw = model.poisson_weight if model.poisson_weight.shape[0] else None
-        net = Network(model.nc_src.shape[0], _ptr(arr(model.nc_src, np.int32), C.c_int32),
-                      _ptr(arr(model.nc_syn, np.int64), C.c_int64), _ptr(arr(model.nc_weight, np.float64), C.c_double),
-                      _ptr(arr(model.nc_delay, np.float64), C.c_double),
-                      _ptr(arr(model.threshold, np.float64), C.c_double), 0.0, model.kick_step.shape[0],
-                      _ptr(arr(model.kick_step, np.int64), C.c_int64), _ptr(arr(model.kick_syn, np.int64), C.c_int64),
-                      _ptr(arr(model.kick_weight, np.float64), C.c_double), float(model.poisson_rate_hz),
-                      _ptr(arr(pw, np.float64), C.c_double) if pw is not None else _dp(),
-                      int(model.seed) & 0xFFFFFFFFFFFFFFFF,
-                      _ptr(arr(model.poisson_key, np.int64), C.c_int64) if model.poisson_key is not None
-                      else _i64p())
+        topo, mtab, n_tables, net = _describe(model, keep)
         opt = Options()
         opt.precision = PRECISION[precision]
         opt.layout = 0
         opt.event_capacity = int(event_capacity)
         opt.max_interval = int(max_interval)
         opt.group_threads = int(group_threads)
+        opt.group_slots = int(group_slots)
+        opt.group_fill_pct = int(group_fill_pct)
         opt.use_graph = 1 if use_graph else 0
         opt.timing = 1 if timing else 0
         opt.validate_only = 1 if validate_only else 0
@@ -217,8 +253,15 @@ class Engine:
             s = stream if stream is not None else torch.cuda.current_stream()
             opt.stream = C.c_void_p(s.cuda_stream)
             self._stream = s
+        self.tune = None
+        if autotune:
+            r = TuneResult()
+            _check(L.cn_autotune(C.byref(topo), mtab, n_tables, C.byref(net), C.byref(opt), self.dt,
+                                 float(tune_budget_ms), C.byref(r)))
+            self.tune = _tune_dict(r)
+            opt.group_threads, opt.group_slots, opt.group_fill_pct = r.group_threads, r.group_slots, r.group_fill_pct
         h = C.c_void_p()
-        _check(L.cn_model_create(C.byref(topo), mtab, len(tables), C.byref(net), C.byref(opt), C.byref(h)))
+        _check(L.cn_model_create(C.byref(topo), mtab, n_tables, C.byref(net), C.byref(opt), C.byref(h)))
         self._h = h
         self.precision = precision
 

@@ -9,10 +9,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -321,6 +324,30 @@ void read_network(cn_model *m, const cn_network *net) {
 }
 
 // ---- device layout: cell groups (bin packing), level order, tables
+
+// Group shapes compiled: T threads x K register slots per thread, capacity T K compartments.
+bool shape_compiled(int T, int K) {
+  if (T == 128) return K == 2 || K == 4 || K == 8;
+  if (T == 256) return K == 1 || K == 2 || K == 4;
+  if (T == 512) return K == 2 || K == 4 || K == 8;
+  return false;
+}
+
+// The default rule for the entries of (T, K) left at 0. Large models take groups of 1024 or more compartments on
+// 512 threads: two slots per thread keep the register budget at four waves per SIMD, which hides the latency of the
+// level sweeps; small models take smaller groups so that there are enough of them to fill the device. K is the
+// smallest compiled slot count whose group holds the largest cell.
+void default_shape(int64_t n_comp, int32_t max_cell, int &T, int &K) {
+  const bool large = n_comp >= (int64_t)1024 * 1024;
+  if (T == 0) T = (large || max_cell > 1024) ? 512 : 256;
+  if (K == 0) {
+    const int kmin = T == 256 ? 1 : 2, kmax = T == 256 ? 4 : 8;
+    K = kmin;
+    while (K < kmax && T * K < max_cell) K *= 2;
+    if (T == 256 && K < 4 && large) K = 4;  // large models on 256 threads: fuller groups
+  }
+}
+
 void build_layout(cn_model *m) {
   const int64_t N = m->n_comp;
   std::vector<int32_t> depth(N, 0), cell_levels(m->n_cells, 0), cell_size(m->n_cells);
@@ -419,24 +446,18 @@ void build_layout(cn_model *m) {
   const Table &syn = m->mech[CN_MECH_EXPSYN];
   for (int64_t k = 0; k < syn.n; ++k) syn_per_cell[cell_of[syn.node[k]]]++;
 
-  // group shape: T threads x K register slots per thread, capacity T*K compartments. Shapes compiled:
-  // T = 128 with K = 2, 4, 8; T = 256 with K = 1, 2, 4; T = 512 with K = 2, 4, 8.
-  // Large models take groups of 1024 or more compartments on 512 threads: two slots per thread keep the register
-  // budget at four waves per SIMD, which hides the latency of the level sweeps; small models take smaller groups
-  // so that there are enough of them to fill the device.
-  const bool large = N >= (int64_t)1024 * 1024;
-  int T = m->opt.group_threads;
-  if (T == 0) T = (large || max_cell > 1024) ? 512 : 256;
-  if (T != 128 && T != 256 && T != 512) throw Err{CN_E_INVALID, "group_threads must be 128, 256 or 512"};
-  const int kmin = T == 256 ? 1 : 2, kmax = T == 256 ? 4 : 8;
-  int K = kmin;
-  while (K < kmax && T * K < max_cell) K *= 2;
+  int T = m->opt.group_threads, K = m->opt.group_slots;
+  default_shape(N, max_cell, T, K);
+  if (!shape_compiled(T, K))
+    throw Err{CN_E_INVALID, "no compiled cell-group shape " + std::to_string(T) + " x " + std::to_string(K)};
   if (T * K < max_cell) throw Err{CN_E_INVALID, "a cell has more compartments (" + std::to_string(max_cell) +
                                                    ") than one cell group holds (" + std::to_string(T * K) + ")"};
-  if (T == 256 && K < 4 && large) K = 4;  // large models on 256 threads: fuller groups
   m->threads = T;
   m->slots = K;
   m->nmax = T * K;
+  // packing capacity: the fill percentage of the group, never below the largest cell
+  const int fill = m->opt.group_fill_pct > 0 ? std::min(100, m->opt.group_fill_pct) : 100;
+  const int64_t cap = std::max<int64_t>(max_cell, (int64_t)m->nmax * fill / 100);
   // synapses per group: up to two LDS rows, so that their terms can be staged on chip
   const int64_t syn_cap = 2 * m->nmax;
 
@@ -468,7 +489,7 @@ void build_layout(cn_model *m) {
     gcells[g].push_back(c);
     gnodes[g] += sz;
     gsyn[g] += sy;
-    const int64_t rem = m->nmax - gnodes[g];
+    const int64_t rem = cap - gnodes[g];
     if (rem > 0) room.emplace(rem, g);
   }
   // heaviest groups first
@@ -605,12 +626,13 @@ static void build_tables(cn_model *m) {
   std::vector<int32_t> grp_of_dev(N);
   for (int64_t g = 0; g < m->n_groups; ++g)
     for (int32_t q = 0; q < m->groups[g].n_nodes; ++q) grp_of_dev[m->groups[g].node_base + q] = (int32_t)g;
-  std::vector<int32_t> first_child(N, -1), n_child(N, 0);
+  std::vector<int32_t> first_child(N, -1), n_child(N, 0), cell_of(N);
+  for (int32_t c = 0; c < m->n_cells; ++c)
+    for (int64_t i = m->cell_off[c]; i < m->cell_off[c + 1]; ++i) cell_of[i] = c;
   for (int64_t dn = 0; dn < N; ++dn) {
     const int64_t i = m->node_of_dev[dn];
     const GroupDesc &gd = m->groups[grp_of_dev[dn]];
-    // caller cell of i
-    const int64_t c = std::upper_bound(m->cell_off.begin(), m->cell_off.end(), i) - m->cell_off.begin() - 1;
+    const int64_t c = cell_of[i];  // caller cell of i
     sa[dn] = 100.0 / m->area[i];
     const int64_t pi = m->tree_par[i];
     if (pi < 0) {
@@ -634,8 +656,6 @@ static void build_tables(cn_model *m) {
   check_tree_layout(m, par, ch);
 
   // density mechanisms: flags, per-node parameters when not uniform, initial states at v_init
-  std::vector<double> st[6];
-  for (auto &s : st) s.assign(N, 0.0);
   double hm, hh, hn;
   hh_inf(m->v_init, hm, hh, hn);
   const int flag_of[4] = {MF_HH, MF_PAS, MF_KM, MF_CAHI};
@@ -650,18 +670,30 @@ static void build_tables(cn_model *m) {
       mf[dn] |= (uint8_t)flag_of[t];
       for (int j = 0; j < N_PARAMS[t]; ++j)
         if (!tb.p[j].uniform) prm[t][j][dn] = tb.p[j].v[k];
-      if (t == CN_MECH_HH) {
-        st[0][dn] = hm;
-        st[1][dn] = hh;
-        st[2][dn] = hn;
-      } else if (t == CN_MECH_KM) {
-        st[3][dn] = km_inf(m->v_init);
-      } else if (t == CN_MECH_CAHI) {
-        st[4][dn] = cahi_inf(m->v_init);
-        st[5][dn] = 5e-5;
-      }
     }
   }
+  // initial states: each mechanism's steady state at v_init where it is present, zero elsewhere
+  auto init_states = [&](auto zero) {
+    using S = decltype(zero);
+    const double kn = km_inf(m->v_init), cm0 = cahi_inf(m->v_init);
+    std::vector<StRec<S>> r(N);
+    for (int64_t dn = 0; dn < N; ++dn) {
+      const uint8_t f = mf[dn];
+      StRec<S> x{};
+      if (f & MF_HH) {
+        x.m = (S)hm;
+        x.h = (S)hh;
+        x.n = (S)hn;
+      }
+      if (f & MF_KM) x.kn = (S)kn;
+      if (f & MF_CAHI) {
+        x.cm = (S)cm0;
+        x.cai = (S)5e-5;
+      }
+      r[dn] = x;
+    }
+    return m->upload(r);
+  };
   KParams &p = m->kp;
   m->host_a = a;
   m->host_b = b;
@@ -676,17 +708,8 @@ static void build_tables(cn_model *m) {
     p.exp_tab = m->upload(et);
   }
   p.n_nodes_total = N;
-  if (m->fp32) {
-    std::vector<StRec<float>> r(N);
-    for (int64_t dn = 0; dn < N; ++dn)
-      r[dn] = StRec<float>{(float)st[0][dn], (float)st[1][dn], (float)st[2][dn], (float)st[3][dn], (float)st[4][dn],
-                           (float)st[5][dn]};
-    p.st = m->upload(r);
-  } else {
-    std::vector<StRec<double>> r(N);
-    for (int64_t dn = 0; dn < N; ++dn) r[dn] = StRec<double>{st[0][dn], st[1][dn], st[2][dn], st[3][dn], st[4][dn], st[5][dn]};
-    p.st = m->upload(r);
-  }
+  if (m->fp32) p.st = init_states(0.0f);
+  else p.st = init_states(0.0);
   // density-mechanism parameters: scalars when every column is uniform, else a per-node table of all columns
   {
     const int cols[N_PRM][2] = {{CN_MECH_HH, 0}, {CN_MECH_HH, 1}, {CN_MECH_HH, 2}, {CN_MECH_HH, 3},
@@ -716,11 +739,11 @@ static void build_tables(cn_model *m) {
 
   // point processes in device order: per node, instances in ascending caller index
   auto order_pp = [&](const Table &tb, std::vector<int64_t> &of_dev, std::vector<int64_t> *dev_of) {
-    std::vector<int64_t> idx(tb.n);
-    std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
-      return m->dev_of_node[tb.node[x]] < m->dev_of_node[tb.node[y]];
-    });
+    // a stable counting sort by device node
+    std::vector<int64_t> start(N + 1, 0), idx(tb.n);
+    for (int64_t k = 0; k < tb.n; ++k) start[m->dev_of_node[tb.node[k]] + 1]++;
+    for (int64_t dn = 0; dn < N; ++dn) start[dn + 1] += start[dn];
+    for (int64_t k = 0; k < tb.n; ++k) idx[start[m->dev_of_node[tb.node[k]]]++] = k;
     of_dev = idx;
     if (dev_of) {
       dev_of->assign(tb.n, 0);
@@ -1462,6 +1485,181 @@ int cn_restore(cn_model *m, double dt, const cn_checkpoint *ck) {
 int cn_set_seed(cn_model *m, uint64_t seed) {
   if (!m) return fail(CN_E_INVALID, "model is NULL");
   m->seed = seed;
+  return CN_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<uint64_t, cn_tune_result> g_tune_cache;
+
+// FNV-1a over the facts that decide the best group shape
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  }
+  template <typename T>
+  void put(T x) { add(&x, sizeof x); }
+};
+
+uint64_t tune_signature(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
+                        const cn_options *opt, double dt) {
+  Fnv f;
+  f.put(topo->n_cells);
+  f.put(topo->n_comp);
+  // cell sizes in quarter-octave bins
+  int64_t hist[128] = {};
+  for (int32_t c = 0; c < topo->n_cells; ++c) {
+    const double n = (double)(topo->cell_offset[c + 1] - topo->cell_offset[c]);
+    hist[std::min<int>(127, (int)std::floor(4.0 * std::log2(std::max(1.0, n))))]++;
+  }
+  f.add(hist, sizeof hist);
+  for (int32_t k = 0; k < n_mechs; ++k) {
+    f.put(mechs[k].type);
+    f.put(mechs[k].n);
+    f.put((int32_t)(mechs[k].node == nullptr));
+  }
+  f.put(net ? net->n_netcon : (int64_t)0);
+  f.put(net ? net->poisson_rate_hz : 0.0);
+  f.put(opt ? opt->precision : 0);
+  f.put(opt ? opt->event_capacity : 0);
+  f.put(opt ? opt->max_interval : 0);
+  f.put(dt);
+  return f.h;
+}
+
+// median interval-kernel time of one shape (ms), or a negative value when the shape cannot run this model
+double time_shape(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
+                  cn_options o, double dt, int T, int K, int fill, int *err, std::string *msg) {
+  o.group_threads = T;
+  o.group_slots = K;
+  o.group_fill_pct = fill;
+  o.timing = 1;
+  o.validate_only = 0;
+  o.fault_inject = 0;
+  cn_model *m = nullptr;
+  int rc = cn_model_create(topo, mechs, n_mechs, net, &o, &m);
+  if (rc == CN_OK) rc = cn_run(m, dt, dt);  // fixes dt and captures the interval graph
+  std::vector<double> ms;
+  if (rc == CN_OK) {
+    const int64_t M = m->kp.M;
+    rc = cn_run(m, (double)M * dt, dt);  // warm-up: the rest of the first interval
+    for (int r = 0; rc == CN_OK && r < 5; ++r) {
+      const double before = m->kernel_ms;
+      rc = cn_run(m, (double)((2 + r) * M) * dt, dt);
+      if (rc == CN_OK) ms.push_back(m->kernel_ms - before);
+    }
+  }
+  if (rc != CN_OK) {
+    *err = rc;
+    *msg = g_err;
+  }
+  cn_model_destroy(m);
+  if (rc != CN_OK || ms.empty()) return -1.0;
+  std::sort(ms.begin(), ms.end());
+  return ms[ms.size() / 2];
+}
+
+}  // namespace
+
+extern "C" {
+
+int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
+                const cn_options *opt, double dt, double budget_ms, cn_tune_result *out) {
+  if (!topo || !out) return fail(CN_E_INVALID, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CN_E_INVALID, "bad dt");
+  if (topo->n_cells <= 0 || !topo->cell_offset) return fail(CN_E_INVALID, "empty model");
+  if (opt && opt->validate_only) return fail(CN_E_STATE, "autotuning needs a device");
+  for (int32_t c = 0; c < topo->n_cells; ++c)
+    if (topo->cell_offset[c + 1] <= topo->cell_offset[c]) return fail(CN_E_INVALID, "cell_offset must be strictly increasing");
+  cn_options base{};
+  if (opt) base = *opt;
+  const uint64_t sig = tune_signature(topo, mechs, n_mechs, net, &base, dt);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(sig);
+    if (it != g_tune_cache.end()) {
+      *out = it->second;
+      out->from_cache = 1;
+      out->n_candidates = 0;
+      return CN_OK;
+    }
+  }
+  int32_t max_cell = 0;
+  for (int32_t c = 0; c < topo->n_cells; ++c)
+    max_cell = std::max<int32_t>(max_cell, (int32_t)(topo->cell_offset[c + 1] - topo->cell_offset[c]));
+  int dT = 0, dK = 0;
+  default_shape(topo->n_comp, max_cell, dT, dK);
+  // candidates: the default first; for each thread count, the smallest slot count that holds the largest cell and
+  // twice that; then the best of these with a 90 % packing fill
+  std::vector<std::array<int, 3>> cand{{dT, dK, 100}};
+  for (int T : {128, 256, 512}) {
+    int K = 0;
+    for (int k : {1, 2, 4, 8})
+      if (shape_compiled(T, k) && T * k >= max_cell) {
+        K = k;
+        break;
+      }
+    if (!K) continue;
+    for (int k : {K, 2 * K}) {
+      if (!shape_compiled(T, k)) continue;
+      const std::array<int, 3> c{T, k, 100};
+      if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    }
+  }
+  cn_tune_result r{};
+  r.signature = sig;
+  r.default_threads = dT;
+  r.default_slots = dK;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto elapsed_ms = [&]() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  };
+  int best = -1;
+  double best_ms = 0.0;
+  auto try_shape = [&](const std::array<int, 3> &c) -> int {
+    int err = CN_OK;
+    std::string msg;
+    const double ms = time_shape(topo, mechs, n_mechs, net, base, dt, c[0], c[1], c[2], &err, &msg);
+    if (ms < 0.0) return err;
+    const int i = r.n_candidates++;
+    r.cand_threads[i] = c[0];
+    r.cand_slots[i] = c[1];
+    r.cand_fill[i] = c[2];
+    r.cand_ms[i] = ms;
+    if (best < 0 || ms < best_ms) {
+      best = i;
+      best_ms = ms;
+    }
+    return CN_OK;
+  };
+  const int rc0 = try_shape(cand[0]);
+  if (rc0 != CN_OK || r.n_candidates == 0) {
+    const std::string msg = g_err;
+    return fail(rc0 != CN_OK ? rc0 : CN_E_DEVICE, "autotune: the default shape failed: " + msg);
+  }
+  r.default_ms = r.cand_ms[0];
+  for (size_t k = 1; k < cand.size() && r.n_candidates < CN_TUNE_MAX_CANDIDATES - 1; ++k) {
+    if (r.n_candidates >= 2 && elapsed_ms() > budget_ms) break;
+    (void)try_shape(cand[k]);
+  }
+  if (elapsed_ms() <= budget_ms || r.n_candidates < 2) {
+    const std::array<int, 3> c{r.cand_threads[best], r.cand_slots[best], 90};
+    (void)try_shape(c);
+  }
+  r.group_threads = r.cand_threads[best];
+  r.group_slots = r.cand_slots[best];
+  r.group_fill_pct = r.cand_fill[best];
+  r.interval_ms = best_ms;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[sig] = r;
+  }
+  *out = r;
   return CN_OK;
 }
 

@@ -65,14 +65,25 @@ struct Math<double> {
   }
   // 1 - exp(-z)
   static __device__ __forceinline__ double omx(double z, const lds_table *et) { return 1.0 - exp_tang(-z, et); }
+  // vtrap(x, y) = y vser(u) near u = x/y = 0: the series 1 - u/2 below |u| = 1e-6 (reading R4)
+  static __device__ __forceinline__ double vser(double u) { return 1.0 - u * 0.5; }
+  static constexpr double VCUT = 1e-6;
 };
 template <>
 struct Math<float> {
   static __device__ __forceinline__ float ex(float x, const lds_table *) { return __expf(x); }
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-  // 1 - exp(-z). At small z the subtraction cancels, but the gate update multiplies it by (x_inf - x): its absolute
-  // error stays below an ulp of the state, the resolution FP32 states have anyway.
-  static __device__ __forceinline__ float omx(float z, const lds_table *) { return 1.0f - __expf(-z); }
+  // 1 - exp(-z). Below z = 1/64 the subtraction would cancel (a relative error of ulp(1)/z, the same sign every step
+  // for slow gates such as km with z near 3e-4); there the series z (1 - z/2 + z^2/6), whose first omitted term is
+  // below 3e-9 relative, is selected without a branch.
+  static __device__ __forceinline__ float omx(float z, const lds_table *) {
+    const float ser = z * (1.0f - z * (0.5f - z * (1.0f / 6.0f)));
+    return z < (1.0f / 64.0f) ? ser : 1.0f - __expf(-z);
+  }
+  // vtrap(x, y) = x / (exp(u) - 1) with u = x/y is y vser(u) near u = 0. In float, exp(u) - 1 loses ulp(1)/|u|
+  // relative accuracy, so below |u| = 1/64 the series 1 - u/2 + u^2/12 (first omitted term u^4/720) is used.
+  static __device__ __forceinline__ float vser(float u) { return 1.0f - u * (0.5f - u * (1.0f / 12.0f)); }
+  static constexpr float VCUT = 1.0f / 64.0f;
 };
 
 // reciprocal of the tree solve: the FP64 kernels use Math<double>::rcp; the FP32-mechanism kernels keep two Newton
@@ -98,15 +109,15 @@ __device__ __forceinline__ void hh_advance(double vd, S q10dt, S &m, S &h, S &n,
   const S u = v + S(40);
   const S xm = -u * S(0.1);  // -(v+40)/10
   const S e40 = M::ex(xm, et);
-  // vtrap(x, y) = x / (exp(x/y) - 1), and its series y (1 - x/y/2) when |x/y| < 1e-6 (selected without a branch)
-  const S am_s = S(1) * (S(1) - xm * S(0.5));
+  // vtrap(x, y) = x / (exp(x/y) - 1), and its series near x = 0 (selected without a branch)
+  const S am_s = S(1) * M::vser(xm);
   const S am_e = S(0.1) * (-u) * M::rcp(e40 - S(1));
-  const S am = fabs(xm) < S(1e-6) ? am_s : am_e;
+  const S am = fabs(xm) < M::VCUT ? am_s : am_e;
   const S xn = xm - S(1.5);  // -(v+55)/10
   const S en = e40 * S(E_NEG_1P5);
-  const S an_s = S(0.1) * (S(1) - xn * S(0.5));
+  const S an_s = S(0.1) * M::vser(xn);
   const S an_e = S(0.01) * (-(u + S(15))) * M::rcp(en - S(1));
-  const S an = fabs(xn) < S(1e-6) ? an_s : an_e;
+  const S an = fabs(xn) < M::VCUT ? an_s : an_e;
   const S bh = M::rcp(e40 * S(E_POS_0P5) + S(1));
   const S w = v + S(65);
   const S bm = S(4) * M::ex(w * S(-1.0 / 18.0), et);

@@ -1,0 +1,70 @@
+"""The cell-group autotuner (cn_autotune): it times candidate shapes on the model itself, caches its choice by the
+model's signature, and the shape it picks changes the grouping only: every shape gives the default shape's results
+bitwise (the arithmetic of a compartment does not depend on the group it sits in)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1901_10975_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _engine(m, **kw):
+    from paper_1901_10975_amd import cn
+    return cn.Engine(m, **kw)
+
+
+def _result(e):
+    return e.voltages(), e.spikes(), [e.mech_state(k, w) for k, w in (("hh", 0), ("km", 0), ("cahi", 1), ("expsyn", 0))]
+
+
+def _same(a, b):
+    assert np.array_equal(a[0], b[0])
+    for x, y in zip(a[1], b[1]):
+        assert np.array_equal(x, y)
+    for x, y in zip(a[2], b[2]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mech"])
+def test_autotune_times_candidates_and_caches(precision):
+    m = synth.cortex_50k(n_cells=3000, seed=17)
+    say(f"autotune {precision}: {m.n_cells} cells, {m.n_comp} compartments")
+    a = _engine(m, precision=precision, autotune=True, tune_budget_ms=120000.0)
+    t = a.tune
+    say(f"  chose {t['group_threads']}x{t['group_slots']} fill {t['group_fill_pct']} at {t['interval_ms']:.3f} ms; "
+        f"default {t['default_threads']}x{t['default_slots']} {t['default_ms']:.3f} ms; "
+        f"{len(t['candidates'])} candidates")
+    assert not t["from_cache"] and len(t["candidates"]) >= 3
+    c0 = t["candidates"][0]
+    assert (c0["threads"], c0["slots"]) == (t["default_threads"], t["default_slots"])
+    assert t["interval_ms"] == min(c["interval_ms"] for c in t["candidates"]) > 0.0
+    info = a.info()
+    assert (info["group_threads"], info["group_slots"]) == (t["group_threads"], t["group_slots"])
+    b = _engine(m, precision=precision, autotune=True)
+    assert b.tune["from_cache"] and b.tune["signature"] == t["signature"]
+    assert (b.tune["group_threads"], b.tune["group_slots"]) == (t["group_threads"], t["group_slots"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mech"])
+def test_every_shape_gives_the_default_results_bitwise(precision):
+    m = synth.cortex_50k(n_cells=600, seed=19)
+    say(f"shapes bitwise, {precision}")
+    ref = _engine(m, precision=precision)
+    ref.run(10.0)
+    r0 = _result(ref)
+    assert r0[1][0].size > 0
+    for T, K, fill in ((128, 8, 100), (256, 4, 100), (512, 2, 90), (512, 4, 100)):
+        e = _engine(m, precision=precision, group_threads=T, group_slots=K, group_fill_pct=fill)
+        e.run(10.0)
+        info = e.info()
+        assert (info["group_threads"], info["group_slots"]) == (T, K)
+        _same(r0, _result(e))
+        say(f"  {T}x{K} fill {fill}: {info['n_groups']} groups, identical")
