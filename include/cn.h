@@ -120,7 +120,8 @@ typedef struct cn_options {
   cn_alloc_fn dev_alloc;  /* optional */
   cn_free_fn dev_free;    /* required when dev_alloc is given */
   void *alloc_ctx;
-  int32_t event_capacity; /* events per cell group per interval, rounded up to a power of two (0: default 512);
+  int32_t event_capacity; /* events per cell group per interval, rounded up to a power of two (0: default 512 per
+                             1024 compartments of group capacity, at least 512);
                              each group holds one interval's events on chip, so larger values cost occupancy */
   int32_t max_interval;   /* upper bound on steps per interval (0: default 64) */
   int32_t group_threads;  /* threads per cell group (0: auto) */
@@ -140,30 +141,36 @@ typedef struct cn_options {
 
 typedef struct cn_model cn_model;
 
-/* Build a model: validate, order and pack cells for the device, upload. On CN_OK *out receives a handle owned by
+/* Build a model (Sec. 3.1 and 3.2: the model is set up once in memory, mechanism instances grouped by type, objects
+ * referred to by integer indices; Sec. 4.4: the node order is the library's own): validate, order and pack cells for
+ * the device, upload. On CN_OK *out receives a handle owned by
  * the library (free with cn_model_destroy). Errors: CN_E_INVALID (bad topology: parent order, non-positive or
  * non-finite area/ri/cm, index out of range, duplicate density instance, unknown type, NaN parameter, ...),
  * CN_E_NOMEM, CN_E_DEVICE. The time step is not fixed here: see cn_run. */
 int cn_model_create(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
                     const cn_options *opt, cn_model **out);
 
-/* Advance the simulation from its current step to step N = llround(tstop / dt) (tstop is absolute simulated time,
+/* Advance the simulation (Sec. 2: the per-step operations, fixed time step; spikes exchanged once per minimum-delay
+ * interval) from its current step to step N = llround(tstop / dt) (tstop is absolute simulated time,
  * t = n * dt exactly; time is an integer step count, never accumulated). The first call fixes dt; a later call
  * with a different dt returns CN_E_STATE, and so does tstop below the current time. Work is queued on the model's
  * stream and the call returns after it completes. Errors: CN_E_CAPACITY (event queue overflow), CN_E_NUMERIC
  * (non-finite voltage, checked at interval ends), CN_E_DEVICE. */
 int cn_run(cn_model *m, double tstop, double dt);
 
-/* Spikes recorded so far, sorted by (step, gid): cell index, step index (the spike happened during the step
+/* Spikes recorded so far (Sec. 2: threshold detection at each cell; the spike output the paper's benchmarks compare
+ * between runs), sorted by (step, gid): cell index, step index (the spike happened during the step
  * ending at that index) and the linearly interpolated crossing time in ms. With gid == NULL only *n_out is set.
  * Otherwise cap must be >= the count (else CN_E_INVALID); any of step/t_interp may be NULL. */
 int cn_spikes(const cn_model *m, int64_t *n_out, int32_t *gid, int64_t *step, double *t_interp, int64_t cap);
 
-/* Membrane potential of every compartment at the current step, in the caller's compartment order (FP64 in both
+/* Membrane potential of every compartment at the current step (Sec. 2, Eq. 1's unknown v), in the caller's
+ * compartment order (FP64 in both
  * precision modes). n_comp must equal the model's count (else CN_E_INVALID). */
 int cn_voltages(const cn_model *m, double *v_out, int64_t n_comp);
 
-/* A mechanism state at the current step in the caller's instance order, as double. type/which select:
+/* A mechanism state at the current step (Sec. 2: channel and synapse states advanced every step; Sec. 4.2: one
+ * table per mechanism type) in the caller's instance order, as double. type/which select:
  * HH 0:m 1:h 2:n; KM 0:n; CAHI 0:m 1:cai; EXPSYN 0:g. n must equal the instance count (else CN_E_INVALID). */
 int cn_mech_state(const cn_model *m, int32_t type, int32_t which, double *out, int64_t n);
 
@@ -230,7 +237,7 @@ typedef struct cn_tune_result {
 int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
                 const cn_options *opt, double dt, double budget_ms, cn_tune_result *out);
 
-/* Model facts for reporting. */
+/* Model facts for reporting (sizes of the device layout of Sec. 4.2 and 4.4 as built here). */
 typedef struct cn_info {
   int64_t n_comp, n_syn, n_netcon, n_groups, step, device_bytes;
   int32_t n_cells, interval_steps, group_threads, group_slots, max_group_nodes, max_levels, ring_slots,
@@ -239,14 +246,15 @@ typedef struct cn_info {
 } cn_info;
 int cn_model_info(const cn_model *m, cn_info *out);
 
-/* With cn_options.timing set: total milliseconds and launch count of the interval kernel over all cn_run calls,
+/* Measurement support (the per-step cost of Sec. 2's operations is what the paper's benchmarks time). With
+ * cn_options.timing set: total milliseconds and launch count of the interval kernel over all cn_run calls,
  * from HIP events recorded on the model's stream around each launch. */
 int cn_stats(const cn_model *m, double *kernel_ms, int64_t *kernel_launches);
 
-/* Free everything the model owns. NULL is a no-op. */
+/* Free everything the model owns (the counterpart of the memory setup of Sec. 3.1). NULL is a no-op. */
 void cn_model_destroy(cn_model *m);
 
-/* Message describing the calling thread's last non-OK status. */
+/* Message describing the calling thread's last non-OK status (error reporting of this boundary). */
 const char *cn_last_error(void);
 
 #ifdef __cplusplus

@@ -1001,7 +1001,8 @@ static void prepare_dt(cn_model *m, double dt) {
     p.bg_thresh = t >= 4294967296.0 ? 4294967296ull : (uint64_t)t;
   }
   // event ring
-  int cap = m->opt.event_capacity > 0 ? m->opt.event_capacity : 512;
+  // default capacity: 512 events per 1024 compartments of group capacity (a group's events grow with its synapses)
+  int cap = m->opt.event_capacity > 0 ? m->opt.event_capacity : std::max(512, m->nmax / 2);
   int pc = 1;
   while (pc < cap) pc <<= 1;
   p.ev_cap = pc;

@@ -111,8 +111,10 @@ def test_restore_matches_the_restored_oracle():
 
 
 def test_reseeded_restart_follows_the_reseeded_oracle():
-    """a restart under a new background key: identical to the oracle restarted under that key, and different from
-    the run that kept the old key"""
+    """a restart under a new background key: it follows the oracle restarted under that key (spikes identical,
+    voltages within the FP64 parity bar, whose sensitivity comes from rounding-level variants of the oracle restarted
+    the same way: the FMA-built oracle and three rounding-probe seeds), and departs from the run that kept the old
+    key"""
     m = _cortex()
     s, end, seed2 = 400, 1200, 987654321
     say(f"reseeded restart at step {s}")
@@ -120,8 +122,11 @@ def test_reseeded_restart_follows_the_reseeded_oracle():
     pre.run_to_step(s)
     ck = pre.checkpoint()
     orc = O.OracleSim(m, n_threads=THREADS)
-    orc.restore(ck)
-    orc.set_seed(seed2)
+    ens = [O.OracleSim(m, n_threads=THREADS, fma=True)] + [O.OracleSim(m, n_threads=THREADS, jitter=j)
+                                                          for j in (1, 2, 3)]
+    for o in [orc] + ens:
+        o.restore(ck)
+        o.set_seed(seed2)
     eng = _engine(m, precision="fp64")
     eng.restore(ck)
     eng.set_seed(seed2)
@@ -131,8 +136,12 @@ def test_reseeded_restart_follows_the_reseeded_oracle():
         orc.run_to_step(n)
         eng.run_to_step(n)
         vo = orc.v()
+        sens = 0.0
+        for o in ens:
+            o.run_to_step(n)
+            sens = max(sens, float(np.max(np.abs(o.v() - vo) / np.maximum(np.abs(vo), 1.0))))
         dev = float(np.max(np.abs(eng.voltages() - vo) / np.maximum(np.abs(vo), 1.0)))
-        assert dev <= 1e-10, (n, dev)
+        assert dev <= max(1e-10, 10.0 * sens), (n, dev, sens)
     same_key.run_to_step(end)
     go, so, _ = orc.spikes()
     gg, sg, _ = eng.spikes()
