@@ -174,6 +174,17 @@ int cn_voltages(const cn_model *m, double *v_out, int64_t n_comp);
  * HH 0:m 1:h 2:n; KM 0:n; CAHI 0:m 1:cai; EXPSYN 0:g. n must equal the instance count (else CN_E_INVALID). */
 int cn_mech_state(const cn_model *m, int32_t type, int32_t which, double *out, int64_t n);
 
+/* The same readout for callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. cn_mech_state stages the gathered states in a device buffer it allocates for
+ * the call; this variant stages them in a buffer of CN_NOALLOC_STATE_MAX doubles (32 MiB) that the library holds on
+ * every device it runs on until the process ends, and calls no hipMalloc, hipFree or allocating library routine.
+ * Arguments, layout and results are those of cn_mech_state. Errors: those of cn_mech_state, and CN_E_CAPACITY when n
+ * exceeds CN_NOALLOC_STATE_MAX (read such a model with cn_mech_state). Every call on one device shares that buffer:
+ * calls that overlap in time on the same device (from different threads) race and must be serialised by the
+ * caller. */
+#define CN_NOALLOC_STATE_MAX 4194304
+int cn_mech_state_noalloc(const cn_model *m, int32_t type, int32_t which, double *out, int64_t n);
+
 /* Checkpoint-restart (Sec. 3.4: a simulation saved at some step continues later, possibly with other stimuli or
  * random streams). A checkpoint is what the readouts give at a step n: the step, cn_voltages, cn_mech_state of every
  * state (the state update pending on the device is applied by that readout, so the states are those of step n) and

@@ -20,8 +20,10 @@ LIB_PATH = os.path.join(PKG, "libcn.so")
 CN_OK, CN_E_INVALID, CN_E_NOMEM, CN_E_DEVICE, CN_E_STATE, CN_E_CAPACITY, CN_E_NUMERIC = range(7)
 MECH_ID = {"hh": 0, "pas": 1, "km": 2, "cahi": 3, "expsyn": 4, "iclamp": 5}
 PRECISION = {"fp64": 0, "fp32_mech": 1}
-EXPORTS = ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_restore", "cn_set_seed",
-           "cn_autotune", "cn_model_info", "cn_stats", "cn_model_destroy", "cn_last_error")
+EXPORTS = ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_mech_state_noalloc",
+           "cn_restore", "cn_set_seed", "cn_autotune", "cn_model_info", "cn_stats", "cn_model_destroy",
+           "cn_last_error")
+NOALLOC_STATE_MAX = 4194304
 STATE_KEYS = (("hh", 0, "hh_m"), ("hh", 1, "hh_h"), ("hh", 2, "hh_n"), ("km", 0, "km_n"), ("cahi", 0, "cahi_m"),
               ("cahi", 1, "cahi_cai"), ("expsyn", 0, "syn_g"))
 
@@ -115,6 +117,7 @@ def lib():
         L.cn_spikes.argtypes = [C.c_void_p, _i64p, _i32p, _i64p, _dp, C.c_int64]
         L.cn_voltages.argtypes = [C.c_void_p, _dp, C.c_int64]
         L.cn_mech_state.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_int64]
+        L.cn_mech_state_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_int64]
         L.cn_restore.argtypes = [C.c_void_p, C.c_double, C.POINTER(Checkpoint)]
         L.cn_set_seed.argtypes = [C.c_void_p, C.c_uint64]
         L.cn_autotune.argtypes = [C.POINTER(Topology), C.POINTER(MechTable), C.c_int32, C.POINTER(Network),
@@ -123,8 +126,8 @@ def lib():
         L.cn_stats.argtypes = [C.c_void_p, _dp, _i64p]
         L.cn_model_destroy.argtypes = [C.c_void_p]
         L.cn_model_destroy.restype = None
-        for f in ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_restore",
-                  "cn_set_seed", "cn_autotune", "cn_model_info", "cn_stats"):
+        for f in ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_mech_state_noalloc",
+                  "cn_restore", "cn_set_seed", "cn_autotune", "cn_model_info", "cn_stats"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -304,6 +307,13 @@ class Engine:
         cnt = self.model.mechs[mech].count(self.model.n_comp)
         out = np.empty(cnt)
         _check(lib().cn_mech_state(self._h, MECH_ID[mech], which, _ptr(out, C.c_double), cnt))
+        return out
+
+    def mech_state_noalloc(self, mech: str, which: int = 0) -> np.ndarray:
+        """as mech_state, through the entry point that allocates no device memory (cn_mech_state_noalloc)"""
+        cnt = self.model.mechs[mech].count(self.model.n_comp)
+        out = np.empty(cnt)
+        _check(lib().cn_mech_state_noalloc(self._h, MECH_ID[mech], which, _ptr(out, C.c_double), cnt))
         return out
 
     def checkpoint(self) -> dict:
