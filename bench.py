@@ -203,6 +203,10 @@ def main():
                     help="run one workload in both precisions and print its line only")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--ordering-study", action="store_true",
+                    help="the node-ordering study: ring_types (131,072 cells x 83 compartments, 10 ms) with 1-64 "
+                         "identical cells per type on the level and the interleaved layout; prints its own line")
+    ap.add_argument("--study-cells", type=int, default=131072)
     args = ap.parse_args()
 
     def log(msg):
@@ -226,6 +230,10 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: {a.numel() * 4} bytes read and written")
         del a, b
+
+    if args.ordering_study:
+        print(json.dumps(ordering_study(log, synth, args.study_cells)), flush=True)
+        return
 
     if args.only == "cortex_200k":
         m = synth.cortex_200k()
@@ -303,6 +311,43 @@ def other_configs(log, synth):
     res["cortex_200k_fp32_mech"]["speedup_vs_fp64"] = (res["cortex_200k_fp32_mech"]["value"]
                                                        / res["cortex_200k_fp64"]["value"])
     return res
+
+
+def ordering_study(log, synth, n_cells):
+    """Sec. 4.4's node-ordering experiment on this engine: ring_types (n_cells x 83 compartments, random branching
+    per type, hh soma, pas dendrites) for 1 to 64 identical cells per type, 10 ms of simulated time after a one-
+    interval warm-up, FP64, on the level layout (constant-depth order, level-parallel solve on chip) and the
+    interleaved layout (one lane per cell, serial solve in global memory). Wall time of the 10 ms and the mean
+    interval-kernel time from HIP events."""
+    import torch
+    from paper_1901_10975_amd import cn
+
+    rows = []
+    for k in (1, 2, 4, 8, 16, 32, 64):
+        m = synth.ring_types(n_cells=n_cells, cells_per_type=k)
+        row = {"cells_per_type": k}
+        for layout in ("level", "interleaved"):
+            eng = cn.Engine(m, precision="fp64", timing=True, layout=layout)
+            eng.run_to_step(40)
+            ms0, l0 = eng.stats()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eng.run_to_step(40 + 400)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ms1, l1 = eng.stats()
+            g, _, _ = eng.spikes()
+            row[layout] = {"wall_ms_10ms": wall * 1e3, "kernel_ms_per_interval": (ms1 - ms0) / max(1, l1 - l0),
+                           "us_per_step": wall / 400 * 1e6, "comp_steps_per_s": m.n_comp * 400 / wall,
+                           "spikes": int(g.size)}
+            log(f"[study] {k} per type, {layout}: 10 ms in {wall * 1e3:.1f} ms ({wall / 400 * 1e6:.1f} us/step), "
+                f"interval kernel {row[layout]['kernel_ms_per_interval']:.3f} ms, {g.size} spikes")
+            eng.close()
+        row["interleaved_over_level"] = row["interleaved"]["wall_ms_10ms"] / row["level"]["wall_ms_10ms"]
+        rows.append(row)
+    return {"study": "node ordering (Sec. 4.4)", "workload": f"ring_types: {n_cells} cells x 83 compartments, "
+            "hh soma, pas dendrites, one ExpSyn per cell in rings of 128, 10 ms at dt 0.025 ms, FP64",
+            "n_comp": n_cells * 83, "rows": rows}
 
 
 def run_gpu_whole(m, precision, tstop, log):

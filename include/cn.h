@@ -59,7 +59,11 @@ enum {
 };
 
 enum { CN_PREC_FP64 = 0, CN_PREC_FP32_MECH = 1 };
-enum { CN_LAYOUT_AUTO = 0, CN_LAYOUT_LEVEL = 1 };
+/* Device node orderings (Sec. 4.4). LEVEL (the default): a workgroup keeps a group of cells on chip for an interval,
+ * compartments ordered level by level (constant depth), the tree solve run level-parallel across the group.
+ * INTERLEAVED: the paper's one-cell-per-thread ordering: up to 64 cells per wave, compartment k of every cell of the
+ * wave side by side in global memory, each lane solving its own cell serially. */
+enum { CN_LAYOUT_AUTO = 0, CN_LAYOUT_LEVEL = 1, CN_LAYOUT_INTERLEAVED = 2 };
 
 /* Cell morphology (Sec. 2: each cell is a tree of compartments). Cells own contiguous compartment ranges
  * [cell_offset[c], cell_offset[c+1]); parent[] is cell-local with -1 at the root (local 0) and parent[i] < i. */
@@ -115,7 +119,7 @@ typedef void (*cn_free_fn)(void *ptr, void *ctx);
 typedef struct cn_options {
   int32_t precision;      /* CN_PREC_FP64 or CN_PREC_FP32_MECH (FP32 mechanism states and rates; voltage,
                              matrix assembly and the tree solve stay FP64) */
-  int32_t layout;         /* CN_LAYOUT_AUTO or CN_LAYOUT_LEVEL */
+  int32_t layout;         /* CN_LAYOUT_AUTO (= LEVEL), CN_LAYOUT_LEVEL or CN_LAYOUT_INTERLEAVED */
   void *stream;           /* hipStream_t for all device work, or NULL for the default stream */
   cn_alloc_fn dev_alloc;  /* optional */
   cn_free_fn dev_free;    /* required when dev_alloc is given */
@@ -222,13 +226,15 @@ int cn_set_seed(cn_model *m, uint64_t seed);
 /* Autotuner of the cell-group shape (Sec. 4.1: cells are grouped so that groups have equal cost; here the group is
  * what one workgroup advances through a minimum-delay interval). Candidate shapes (threads x compartments per thread,
  * and a packing fill) that hold the largest cell are each built as a model from the same description and options,
- * run for one warm-up interval and then timed over five intervals with HIP events on the model's stream; the shape
- * with the lowest median interval time wins. Results are cached in the process by a signature of the model
+ * run for one warm-up interval and then timed over five intervals with HIP events on the model's stream; the
+ * interleaved layout (one lane per cell) is timed as one more candidate unless the caller fixed a layout. The
+ * candidate with the lowest median interval time wins. Results are cached in the process by a signature of the model
  * (cell-size histogram, synapse and mechanism counts, precision, dt, interval and capacity options): a second call
  * with the same signature returns the cached choice without timing. budget_ms bounds the wall time spent timing
  * (at least the default shape and one other are always timed). The caller then creates its model with
- * opt.group_threads, opt.group_slots and opt.group_fill_pct set from the result. The shape changes only the
- * grouping, never the arithmetic of a compartment, so a tuned model's results equal the default model's bitwise.
+ * opt.layout, opt.group_threads, opt.group_slots and opt.group_fill_pct set from the result. A level-layout shape
+ * changes only the grouping, never the arithmetic of a compartment, so such a tuned model's results equal the
+ * default model's bitwise; the interleaved layout solves each tree in another order (results within rounding).
  * Arguments as for cn_model_create (borrowed); opt->group_threads/group_slots/group_fill_pct are ignored. Errors:
  * those of cn_model_create and cn_run for the default shape (a failing non-default candidate is skipped). */
 #define CN_TUNE_MAX_CANDIDATES 16
@@ -237,12 +243,12 @@ typedef struct cn_tune_result {
   int32_t default_threads, default_slots;              /* the shape of the default rule */
   int32_t n_candidates;                                /* shapes timed by this call (0 when taken from the cache) */
   int32_t from_cache;
-  int32_t pad;
+  int32_t layout;                                      /* the chosen layout (CN_LAYOUT_LEVEL or _INTERLEAVED) */
   double interval_ms;                                  /* median interval time of the chosen shape */
   double default_ms;                                   /* median interval time of the default shape */
   uint64_t signature;
   int32_t cand_threads[CN_TUNE_MAX_CANDIDATES], cand_slots[CN_TUNE_MAX_CANDIDATES],
-      cand_fill[CN_TUNE_MAX_CANDIDATES];
+      cand_fill[CN_TUNE_MAX_CANDIDATES], cand_layout[CN_TUNE_MAX_CANDIDATES];
   double cand_ms[CN_TUNE_MAX_CANDIDATES];
 } cn_tune_result;
 int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
@@ -254,6 +260,8 @@ typedef struct cn_info {
   int32_t n_cells, interval_steps, group_threads, group_slots, max_group_nodes, max_levels, ring_slots,
       event_capacity, precision, lds_bytes;
   double dt;
+  int32_t layout; /* CN_LAYOUT_LEVEL or CN_LAYOUT_INTERLEAVED; for INTERLEAVED, group_threads is 64 (one lane per
+                     cell) and group_slots the largest cell's compartment count */
 } cn_info;
 int cn_model_info(const cn_model *m, cn_info *out);
 

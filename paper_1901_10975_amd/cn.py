@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(PKG, "libcn.so")
 CN_OK, CN_E_INVALID, CN_E_NOMEM, CN_E_DEVICE, CN_E_STATE, CN_E_CAPACITY, CN_E_NUMERIC = range(7)
 MECH_ID = {"hh": 0, "pas": 1, "km": 2, "cahi": 3, "expsyn": 4, "iclamp": 5}
 PRECISION = {"fp64": 0, "fp32_mech": 1}
+LAYOUT = {"auto": 0, "level": 1, "interleaved": 2}
 EXPORTS = ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_mech_state_noalloc",
            "cn_restore", "cn_set_seed", "cn_autotune", "cn_model_info", "cn_stats", "cn_model_destroy",
            "cn_last_error")
@@ -79,10 +80,10 @@ TUNE_MAX = 16
 class TuneResult(C.Structure):
     _fields_ = [("group_threads", C.c_int32), ("group_slots", C.c_int32), ("group_fill_pct", C.c_int32),
                 ("default_threads", C.c_int32), ("default_slots", C.c_int32), ("n_candidates", C.c_int32),
-                ("from_cache", C.c_int32), ("pad", C.c_int32), ("interval_ms", C.c_double),
+                ("from_cache", C.c_int32), ("layout", C.c_int32), ("interval_ms", C.c_double),
                 ("default_ms", C.c_double), ("signature", C.c_uint64), ("cand_threads", C.c_int32 * TUNE_MAX),
                 ("cand_slots", C.c_int32 * TUNE_MAX), ("cand_fill", C.c_int32 * TUNE_MAX),
-                ("cand_ms", C.c_double * TUNE_MAX)]
+                ("cand_layout", C.c_int32 * TUNE_MAX), ("cand_ms", C.c_double * TUNE_MAX)]
 
 
 class Info(C.Structure):
@@ -91,7 +92,7 @@ class Info(C.Structure):
                 ("interval_steps", C.c_int32), ("group_threads", C.c_int32), ("group_slots", C.c_int32),
                 ("max_group_nodes", C.c_int32), ("max_levels", C.c_int32), ("ring_slots", C.c_int32),
                 ("event_capacity", C.c_int32), ("precision", C.c_int32), ("lds_bytes", C.c_int32),
-                ("dt", C.c_double)]
+                ("dt", C.c_double), ("layout", C.c_int32)]
 
 
 _lib = None
@@ -212,11 +213,13 @@ def _describe(model: "synth.Model", keep: list):
 
 def _tune_dict(r: TuneResult) -> dict:
     k = r.n_candidates
-    return {"group_threads": r.group_threads, "group_slots": r.group_slots, "group_fill_pct": r.group_fill_pct,
-            "interval_ms": r.interval_ms, "default_threads": r.default_threads, "default_slots": r.default_slots,
-            "default_ms": r.default_ms, "from_cache": bool(r.from_cache), "signature": f"{r.signature:016x}",
-            "candidates": [{"threads": r.cand_threads[i], "slots": r.cand_slots[i], "fill_pct": r.cand_fill[i],
-                            "interval_ms": r.cand_ms[i]} for i in range(k)]}
+    names = {v: n for n, v in LAYOUT.items()}
+    return {"layout": names[r.layout], "group_threads": r.group_threads, "group_slots": r.group_slots,
+            "group_fill_pct": r.group_fill_pct, "interval_ms": r.interval_ms, "default_threads": r.default_threads,
+            "default_slots": r.default_slots, "default_ms": r.default_ms, "from_cache": bool(r.from_cache),
+            "signature": f"{r.signature:016x}",
+            "candidates": [{"layout": names[r.cand_layout[i]], "threads": r.cand_threads[i], "slots": r.cand_slots[i],
+                            "fill_pct": r.cand_fill[i], "interval_ms": r.cand_ms[i]} for i in range(k)]}
 
 
 class Engine:
@@ -227,7 +230,8 @@ class Engine:
     def __init__(self, model: "synth.Model", precision: str = "fp64", use_graph: bool = True, timing: bool = False,
                  event_capacity: int = 0, max_interval: int = 0, group_threads: int = 0, group_slots: int = 0,
                  group_fill_pct: int = 0, use_torch: bool = True, stream=None, validate_only: bool = False,
-                 fault_inject: int = 0, autotune: bool = False, tune_budget_ms: float = 60000.0):
+                 fault_inject: int = 0, autotune: bool = False, tune_budget_ms: float = 60000.0,
+                 layout: str = "auto"):
         L = lib()
         self.model = model
         self.dt = float(model.dt)
@@ -235,7 +239,7 @@ class Engine:
         topo, mtab, n_tables, net = _describe(model, keep)
         opt = Options()
         opt.precision = PRECISION[precision]
-        opt.layout = 0
+        opt.layout = LAYOUT[layout]
         opt.event_capacity = int(event_capacity)
         opt.max_interval = int(max_interval)
         opt.group_threads = int(group_threads)
@@ -262,6 +266,7 @@ class Engine:
             _check(L.cn_autotune(C.byref(topo), mtab, n_tables, C.byref(net), C.byref(opt), self.dt,
                                  float(tune_budget_ms), C.byref(r)))
             self.tune = _tune_dict(r)
+            opt.layout = r.layout
             opt.group_threads, opt.group_slots, opt.group_fill_pct = r.group_threads, r.group_slots, r.group_fill_pct
         h = C.c_void_p()
         _check(L.cn_model_create(C.byref(topo), mtab, n_tables, C.byref(net), C.byref(opt), C.byref(h)))

@@ -26,6 +26,8 @@
 namespace cn {
 hipError_t launch_interval(const KParams &p, bool fp32, int threads, int slots, int lds_bytes, hipStream_t st);
 hipError_t set_interval_lds(bool fp32, int threads, int slots, bool uni, int lds_bytes);
+hipError_t launch_lpc(const KParams &p, bool fp32, int lds_bytes, hipStream_t st);
+hipError_t set_lpc_lds(bool fp32, bool uni, int lds_bytes);
 int interval_row_bytes(int nmax);
 hipError_t launch_advance(int64_t *ctl, int32_t M, hipStream_t st);
 hipError_t launch_fanout(const KParams &p, hipStream_t st);
@@ -117,6 +119,8 @@ struct cn_model {
 
   // ---- layout
   int threads = 256, slots = 4, nmax = 1024;
+  bool lpc = false;     // interleaved layout, one lane per cell (else the level layout)
+  int64_t n_dev = 0;    // device node slots (the compartments, plus padding in the interleaved layout)
   int64_t n_groups = 0;
   std::vector<GroupDesc> groups;
   std::vector<int32_t> lvl_start;
@@ -498,6 +502,7 @@ void build_layout(cn_model *m) {
   std::stable_sort(gorder.begin(), gorder.end(), [&](int32_t a, int32_t b) { return gnodes[a] > gnodes[b]; });
 
   m->n_groups = (int64_t)gcells.size();
+  m->n_dev = N;
   m->groups.assign(m->n_groups, GroupDesc{});
   m->dev_of_node.assign(N, -1);
   m->node_of_dev.assign(N, -1);
@@ -557,6 +562,62 @@ void build_layout(cn_model *m) {
   }
 }
 
+// ---- interleaved layout (one lane per cell): cells in groups of 64 consecutive cells, ordered by size (stable, so
+// identical cells given next to each other stay together), compartment k of lane j at node_base + 64 k + j
+void build_layout_lpc(cn_model *m) {
+  const int64_t N = m->n_comp;
+  std::vector<int32_t> order(m->n_cells);
+  std::iota(order.begin(), order.end(), 0);
+  auto size = [&](int32_t c) { return m->cell_off[c + 1] - m->cell_off[c]; };
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return size(a) > size(b); });
+  m->tree_par.assign(N, -1);
+  m->cell_root.assign(m->n_cells, 0);
+  for (int32_t c = 0; c < m->n_cells; ++c) {
+    m->cell_root[c] = m->cell_off[c];
+    for (int64_t i = m->cell_off[c] + 1; i < m->cell_off[c + 1]; ++i) m->tree_par[i] = m->cell_off[c] + m->parent[i];
+  }
+  m->n_groups = (m->n_cells + 63) / 64;
+  m->groups.assign(m->n_groups, GroupDesc{});
+  m->cell_of_devcell.assign(order.begin(), order.end());
+  m->lvl_start.clear();
+  int64_t base = 0;
+  int32_t max_kn = 0;
+  for (int64_t g = 0; g < m->n_groups; ++g) {
+    GroupDesc &gd = m->groups[g];
+    gd.cell_base = (int32_t)(64 * g);
+    gd.n_cells = (int32_t)std::min<int64_t>(64, m->n_cells - 64 * g);
+    int32_t kn = 0;
+    for (int32_t j = 0; j < gd.n_cells; ++j) kn = std::max<int32_t>(kn, (int32_t)size(order[gd.cell_base + j]));
+    gd.node_base = base;
+    gd.n_levels = kn;
+    gd.n_nodes = 64 * kn;
+    gd.lvl_base = 0;
+    base += gd.n_nodes;
+    max_kn = std::max(max_kn, kn);
+  }
+  m->n_dev = base;
+  if (m->n_dev >= (int64_t)INT32_MAX) throw Err{CN_E_INVALID, "model too large for the interleaved layout"};
+  m->dev_of_node.assign(N, -1);
+  m->node_of_dev.assign(m->n_dev, -1);
+  for (int64_t g = 0; g < m->n_groups; ++g) {
+    const GroupDesc &gd = m->groups[g];
+    for (int32_t j = 0; j < gd.n_cells; ++j) {
+      const int32_t c = order[gd.cell_base + j];
+      for (int64_t k = 0; k < size(c); ++k) {
+        const int64_t dn = gd.node_base + 64 * k + j;
+        m->dev_of_node[m->cell_off[c] + k] = dn;
+        m->node_of_dev[dn] = m->cell_off[c] + k;
+      }
+    }
+  }
+  m->threads = 64;
+  m->slots = max_kn;
+  m->nmax = 64 * max_kn;
+  m->max_levels = max_kn;
+  m->max_group_nodes = m->nmax;
+  m->max_group_cells = 64;
+}
+
 }  // namespace
 
 // ---- invariants the interval kernel relies on for every index it forms (checked on the host before upload)
@@ -595,6 +656,36 @@ static void check_tree_layout(const cn_model *m, const std::vector<int32_t> &par
   if (total != m->n_comp) layout_fail("node total");
 }
 
+// the interleaved layout: group g holds 64 lanes x n_levels slots from node_base on, slot 64 k + lane; lane j < n_cells
+// holds its cell's compartments at k = 0 .. size-1 (caller order, parent index below the compartment's), padding after
+static void check_lpc_layout(const cn_model *m, const std::vector<int32_t> &par) {
+  int64_t total = 0, real = 0;
+  for (int64_t g = 0; g < m->n_groups; ++g) {
+    const GroupDesc &gd = m->groups[g];
+    if (gd.node_base != total) layout_fail("node base");
+    if (gd.n_cells < 1 || gd.n_cells > 64 || gd.n_levels < 1 || gd.n_nodes != 64 * gd.n_levels) layout_fail("group size");
+    for (int32_t j = 0; j < 64; ++j) {
+      int64_t size = 0;
+      if (j < gd.n_cells) {
+        const int32_t c = m->cell_of_devcell[gd.cell_base + j];
+        size = m->cell_off[c + 1] - m->cell_off[c];
+        if (size > gd.n_levels) layout_fail("cell larger than its group's slots");
+      }
+      for (int32_t k = 0; k < gd.n_levels; ++k) {
+        const int64_t dn = gd.node_base + 64 * (int64_t)k + j;
+        const int64_t i = m->node_of_dev[dn];
+        if ((k < size) != (i >= 0)) layout_fail("padding slot");
+        if (k < size && i != m->cell_off[m->cell_of_devcell[gd.cell_base + j]] + k) layout_fail("compartment slot");
+        if (k > 0 && (par[dn] < 0 || par[dn] >= (k < size ? k : 1))) layout_fail("parent index");
+        if (k == 0 && par[dn] != (i >= 0 ? -1 : 0)) layout_fail("root parent");
+      }
+      real += size;
+    }
+    total += gd.n_nodes;
+  }
+  if (total != m->n_dev || real != m->n_comp) layout_fail("node total");
+}
+
 static void check_ranges(const cn_model *m, const std::vector<int2> &r, bool syn) {
   int64_t covered_total = 0;
   for (int64_t g = 0; g < m->n_groups; ++g) {
@@ -616,21 +707,22 @@ static void check_ranges(const cn_model *m, const std::vector<int2> &r, bool syn
 
 // ---- tables that do not depend on dt
 static void build_tables(cn_model *m) {
-  const int64_t N = m->n_comp;
+  const int64_t N = m->n_dev;  // device node slots; a slot with no compartment (padding) is inert
   const bool f32 = m->fp32;
-  std::vector<double> a(N), b(N), sa(N);
-  std::vector<int32_t> par(N);
-  std::vector<uint32_t> ch(N);
+  std::vector<double> a(N, 0.0), b(N, 0.0), sa(N, 0.0);
+  std::vector<int32_t> par(N, 0);
+  std::vector<uint32_t> ch(N, 0);
   std::vector<uint8_t> mf(N, 0);
   // group of each device node, and group-local index
   std::vector<int32_t> grp_of_dev(N);
   for (int64_t g = 0; g < m->n_groups; ++g)
     for (int32_t q = 0; q < m->groups[g].n_nodes; ++q) grp_of_dev[m->groups[g].node_base + q] = (int32_t)g;
-  std::vector<int32_t> first_child(N, -1), n_child(N, 0), cell_of(N);
+  std::vector<int32_t> first_child(N, -1), n_child(N, 0), cell_of(m->n_comp);
   for (int32_t c = 0; c < m->n_cells; ++c)
     for (int64_t i = m->cell_off[c]; i < m->cell_off[c + 1]; ++i) cell_of[i] = c;
   for (int64_t dn = 0; dn < N; ++dn) {
     const int64_t i = m->node_of_dev[dn];
+    if (i < 0) continue;  // padding
     const GroupDesc &gd = m->groups[grp_of_dev[dn]];
     const int64_t c = cell_of[i];  // caller cell of i
     sa[dn] = 100.0 / m->area[i];
@@ -645,15 +737,23 @@ static void build_tables(cn_model *m) {
       a[dn] = -100.0 * g / m->area[pi];
       b[dn] = -100.0 * g / m->area[i];
       const int64_t pd = m->dev_of_node[pi];
+      if (m->lpc) {  // the parent's compartment index within the cell (its slot is 64 index + lane)
+        par[dn] = (int32_t)(pi - m->cell_off[c]);
+        continue;
+      }
       par[dn] = (int32_t)(pd - gd.node_base);
       const int32_t ql = (int32_t)(dn - gd.node_base);
       if (first_child[pd] < 0 || ql < first_child[pd]) first_child[pd] = ql;
       n_child[pd]++;
     }
   }
-  for (int64_t dn = 0; dn < N; ++dn)
-    ch[dn] = (uint32_t)(first_child[dn] < 0 ? 0 : first_child[dn]) | ((uint32_t)n_child[dn] << 16);
-  check_tree_layout(m, par, ch);
+  if (m->lpc) {
+    check_lpc_layout(m, par);
+  } else {
+    for (int64_t dn = 0; dn < N; ++dn)
+      ch[dn] = (uint32_t)(first_child[dn] < 0 ? 0 : first_child[dn]) | ((uint32_t)n_child[dn] << 16);
+    check_tree_layout(m, par, ch);
+  }
 
   // density mechanisms: flags, per-node parameters when not uniform, initial states at v_init
   double hm, hh, hn;
@@ -702,6 +802,11 @@ static void build_tables(cn_model *m) {
   m->host_par = par;
   m->host_ch = ch;
   p.v = m->upload(std::vector<double>(N, m->v_init));
+  if (m->lpc) {
+    p.lw_d = static_cast<double *>(m->dalloc(N * sizeof(double)));
+    p.lw_r = static_cast<double *>(m->dalloc(N * sizeof(double)));
+    p.lw_dv = static_cast<double *>(m->dalloc(N * sizeof(double)));
+  }
   {
     std::vector<double> et(64);
     for (int j = 0; j < 64; ++j) et[j] = (double)exp2l((long double)j / 64.0L);
@@ -923,10 +1028,16 @@ static void build_tables(cn_model *m) {
   }
 }
 
+// the kernel that advances every group through one chunk
+static hipError_t launch_chunk(cn_model *m) {
+  if (m->lpc) return launch_lpc(m->kp, m->fp32, m->lds_bytes, m->stream);
+  return launch_interval(m->kp, m->fp32, m->threads, m->slots, m->lds_bytes, m->stream);
+}
+
 // ---- tables that depend on dt; allocation of the event ring and spike buffers; graph capture
 static void prepare_dt(cn_model *m, double dt) {
   KParams &p = m->kp;
-  const int64_t N = m->n_comp;
+  const int64_t N = m->n_dev;
   p.dt = dt;
   p.q10dt = std::pow(3.0, (m->celsius - 6.3) / 10.0) * dt;
   p.ca_fm = 1.0 - std::exp(-dt / 1.0);
@@ -937,7 +1048,8 @@ static void prepare_dt(cn_model *m, double dt) {
     // capacitance term 1e-3 cm/dt (S/cm^2) and the node's own axial coupling -b
     std::vector<NodeRec> rec(N);
     for (int64_t dn = 0; dn < N; ++dn) {
-      k[dn] = 1e-3 * m->cm[m->node_of_dev[dn]] / dt - m->host_b[dn];
+      const int64_t i = m->node_of_dev[dn];
+      k[dn] = i < 0 ? 1.0 : 1e-3 * m->cm[i] / dt - m->host_b[dn];  // a padding slot solves d = 1, rhs = 0
       rec[dn] = NodeRec{m->host_a[dn], m->host_b[dn], k[dn], m->host_sa[dn]};
     }
     p.nrec = m->upload(rec);
@@ -1002,7 +1114,9 @@ static void prepare_dt(cn_model *m, double dt) {
   }
   // event ring
   // default capacity: 512 events per 1024 compartments of group capacity (a group's events grow with its synapses)
-  int cap = m->opt.event_capacity > 0 ? m->opt.event_capacity : std::max(512, m->nmax / 2);
+  // (interleaved layout: a quarter of the largest group's synapse count, at least 512)
+  int cap = m->opt.event_capacity > 0 ? m->opt.event_capacity
+                                      : (m->lpc ? std::max(512, m->max_group_syn / 4) : std::max(512, m->nmax / 2));
   int pc = 1;
   while (pc < cap) pc <<= 1;
   p.ev_cap = pc;
@@ -1042,7 +1156,7 @@ static void prepare_dt(cn_model *m, double dt) {
   // constants (three doubles and three 32-bit indices) for groups of up to 2048 nodes, event keys, step segments,
   // level starts, background bits, counters
   p.nmax = m->nmax;
-  int off = interval_row_bytes(m->nmax);
+  int off = m->lpc ? 0 : interval_row_bytes(m->nmax);  // the interleaved layout keeps no node rows on chip
   p.lds_ev_off = off;
   off += p.ev_cap * 8;
   p.lds_seg_off = off;
@@ -1065,13 +1179,14 @@ static void prepare_dt(cn_model *m, double dt) {
   if (m->lds_bytes > 160 * 1024)
     throw Err{CN_E_INVALID, "cell groups need " + std::to_string(m->lds_bytes) + " bytes of LDS (event_capacity "
                                 "or synapses per group too large)"};
-  HIPCHK(set_interval_lds(m->fp32, m->threads, m->slots, p.prm == nullptr, m->lds_bytes));
+  if (m->lpc) HIPCHK(set_lpc_lds(m->fp32, p.prm == nullptr, m->lds_bytes));
+  else HIPCHK(set_interval_lds(m->fp32, m->threads, m->slots, p.prm == nullptr, m->lds_bytes));
   HIPCHK(hipStreamSynchronize(m->stream));
   if (m->opt.use_graph) {
     HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
     // whatever fails below, the capture is ended before the error is reported, so that the caller's stream never
     // stays in capture mode
-    hipError_t e1 = launch_interval(m->kp, m->fp32, m->threads, m->slots, m->lds_bytes, m->stream);
+    hipError_t e1 = launch_chunk(m);
     if (e1 == hipSuccess) e1 = launch_fanout(m->kp, m->stream);
     hipError_t e2 = launch_advance(p.ctl, p.M, m->stream);
     if (m->opt.fault_inject == 2 && e2 == hipSuccess) e2 = hipErrorLaunchFailure;
@@ -1190,7 +1305,9 @@ int cn_model_create(const cn_topology *topo, const cn_mech_table *mechs, int32_t
     if (opt) m->opt = *opt;
     if (m->opt.precision != CN_PREC_FP64 && m->opt.precision != CN_PREC_FP32_MECH)
       throw Err{CN_E_INVALID, "unknown precision"};
-    if (m->opt.layout != CN_LAYOUT_AUTO && m->opt.layout != CN_LAYOUT_LEVEL) throw Err{CN_E_INVALID, "unknown layout"};
+    if (m->opt.layout != CN_LAYOUT_AUTO && m->opt.layout != CN_LAYOUT_LEVEL && m->opt.layout != CN_LAYOUT_INTERLEAVED)
+      throw Err{CN_E_INVALID, "unknown layout"};
+    m->lpc = m->opt.layout == CN_LAYOUT_INTERLEAVED;
     if (m->opt.dev_alloc && !m->opt.dev_free) throw Err{CN_E_INVALID, "dev_alloc without dev_free"};
     m->fp32 = m->opt.precision == CN_PREC_FP32_MECH;
     if (topo->n_cells <= 0 || topo->n_comp <= 0) throw Err{CN_E_INVALID, "empty model"};
@@ -1238,7 +1355,8 @@ int cn_model_create(const cn_topology *topo, const cn_mech_table *mechs, int32_t
       m->own_stream = true;
     }
     if (!m->dry) HIPCHK(hipGetDevice(&m->device));
-    build_layout(m);
+    if (m->lpc) build_layout_lpc(m);
+    else build_layout(m);
     build_tables(m);
     if (!m->dry) HIPCHK(hipStreamSynchronize(m->stream));
   } catch (const Err &e) {
@@ -1294,7 +1412,7 @@ int cn_run(cn_model *m, double tstop, double dt) {
       if (m->gexec) {
         HIPCHK(hipGraphLaunch(m->gexec, m->stream));
       } else {
-        HIPCHK(launch_interval(p, m->fp32, m->threads, m->slots, m->lds_bytes, m->stream));
+        HIPCHK(launch_chunk(m));
         HIPCHK(launch_fanout(p, m->stream));
         HIPCHK(launch_advance(p.ctl, p.M, m->stream));
       }
@@ -1345,9 +1463,9 @@ int cn_voltages(const cn_model *m, double *v_out, int64_t n_comp) {
   if (m->dry) return fail(CN_E_STATE, "model was built with validate_only");
   if (n_comp != m->n_comp) return fail(CN_E_INVALID, "n_comp does not match the model");
   try {
-    std::vector<double> dv(m->n_comp);
+    std::vector<double> dv(m->n_dev);
     HIPCHK(hipStreamSynchronize(m->stream));
-    HIPCHK(hipMemcpy(dv.data(), m->kp.v, m->n_comp * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(dv.data(), m->kp.v, m->n_dev * sizeof(double), hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < m->n_comp; ++i) v_out[i] = dv[m->dev_of_node[i]];
   } catch (const Err &e) {
     return fail(e.code, e.msg);
@@ -1400,11 +1518,11 @@ int cn_restore(cn_model *m, double dt, const cn_checkpoint *ck) {
     }
     touched = true;
     KParams &p = m->kp;
-    const int64_t N = m->n_comp;
+    const int64_t N = m->n_dev;
     HIPCHK(hipStreamSynchronize(m->stream));
     {
-      std::vector<double> dv(N);
-      for (int64_t i = 0; i < N; ++i) dv[m->dev_of_node[i]] = ck->v[i];
+      std::vector<double> dv(N, m->v_init);
+      for (int64_t i = 0; i < m->n_comp; ++i) dv[m->dev_of_node[i]] = ck->v[i];
       HIPCHK(hipMemcpy(p.v, dv.data(), N * sizeof(double), hipMemcpyHostToDevice));
     }
     // channel states: the device copy (initial values where a mechanism is absent) with the checkpoint's values
@@ -1527,6 +1645,7 @@ uint64_t tune_signature(const cn_topology *topo, const cn_mech_table *mechs, int
   f.put(net ? net->n_netcon : (int64_t)0);
   f.put(net ? net->poisson_rate_hz : 0.0);
   f.put(opt ? opt->precision : 0);
+  f.put(opt ? opt->layout : 0);
   f.put(opt ? opt->event_capacity : 0);
   f.put(opt ? opt->max_interval : 0);
   f.put(dt);
@@ -1535,7 +1654,8 @@ uint64_t tune_signature(const cn_topology *topo, const cn_mech_table *mechs, int
 
 // median interval-kernel time of one shape (ms), or a negative value when the shape cannot run this model
 double time_shape(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
-                  cn_options o, double dt, int T, int K, int fill, int *err, std::string *msg) {
+                  cn_options o, double dt, int layout, int T, int K, int fill, int *err, std::string *msg) {
+  o.layout = layout;
   o.group_threads = T;
   o.group_slots = K;
   o.group_fill_pct = fill;
@@ -1597,7 +1717,8 @@ int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_m
   default_shape(topo->n_comp, max_cell, dT, dK);
   // candidates: the default first; for each thread count, the smallest slot count that holds the largest cell and
   // twice that; then the best of these with a 90 % packing fill
-  std::vector<std::array<int, 3>> cand{{dT, dK, 100}};
+  const int L = CN_LAYOUT_LEVEL;
+  std::vector<std::array<int, 4>> cand{{L, dT, dK, 100}};
   for (int T : {128, 256, 512}) {
     int K = 0;
     for (int k : {1, 2, 4, 8})
@@ -1608,10 +1729,12 @@ int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_m
     if (!K) continue;
     for (int k : {K, 2 * K}) {
       if (!shape_compiled(T, k)) continue;
-      const std::array<int, 3> c{T, k, 100};
+      const std::array<int, 4> c{L, T, k, 100};
       if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
     }
   }
+  if (base.layout == CN_LAYOUT_AUTO) cand.push_back({CN_LAYOUT_INTERLEAVED, 0, 0, 100});
+  if (base.layout == CN_LAYOUT_INTERLEAVED) cand = {{CN_LAYOUT_INTERLEAVED, 0, 0, 100}};
   cn_tune_result r{};
   r.signature = sig;
   r.default_threads = dT;
@@ -1622,15 +1745,16 @@ int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_m
   };
   int best = -1;
   double best_ms = 0.0;
-  auto try_shape = [&](const std::array<int, 3> &c) -> int {
+  auto try_shape = [&](const std::array<int, 4> &c) -> int {
     int err = CN_OK;
     std::string msg;
-    const double ms = time_shape(topo, mechs, n_mechs, net, base, dt, c[0], c[1], c[2], &err, &msg);
+    const double ms = time_shape(topo, mechs, n_mechs, net, base, dt, c[0], c[1], c[2], c[3], &err, &msg);
     if (ms < 0.0) return err;
     const int i = r.n_candidates++;
-    r.cand_threads[i] = c[0];
-    r.cand_slots[i] = c[1];
-    r.cand_fill[i] = c[2];
+    r.cand_layout[i] = c[0];
+    r.cand_threads[i] = c[1];
+    r.cand_slots[i] = c[2];
+    r.cand_fill[i] = c[3];
     r.cand_ms[i] = ms;
     if (best < 0 || ms < best_ms) {
       best = i;
@@ -1648,10 +1772,11 @@ int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_m
     if (r.n_candidates >= 2 && elapsed_ms() > budget_ms) break;
     (void)try_shape(cand[k]);
   }
-  if (elapsed_ms() <= budget_ms || r.n_candidates < 2) {
-    const std::array<int, 3> c{r.cand_threads[best], r.cand_slots[best], 90};
+  if (r.cand_layout[best] == L && (elapsed_ms() <= budget_ms || r.n_candidates < 2)) {
+    const std::array<int, 4> c{L, r.cand_threads[best], r.cand_slots[best], 90};
     (void)try_shape(c);
   }
+  r.layout = r.cand_layout[best];
   r.group_threads = r.cand_threads[best];
   r.group_slots = r.cand_slots[best];
   r.group_fill_pct = r.cand_fill[best];
@@ -1684,6 +1809,7 @@ int cn_model_info(const cn_model *m, cn_info *o) {
   o->precision = m->fp32 ? CN_PREC_FP32_MECH : CN_PREC_FP64;
   o->lds_bytes = m->lds_bytes;
   o->dt = m->dt;
+  o->layout = m->lpc ? CN_LAYOUT_INTERLEAVED : CN_LAYOUT_LEVEL;
   return CN_OK;
 }
 

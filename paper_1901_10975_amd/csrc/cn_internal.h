@@ -131,6 +131,8 @@ struct KParams {
   int32_t *flags;          // [0] event overflow, [1] spike record overflow, [2] non-finite voltage
   int64_t *ctl;            // [0] first step of the next chunk, [1] target step, [2] the step whose channel states
                            // carry no pending update (0, or the step of a restart), [3] key of the background streams
+  // interleaved layout (one lane per cell): per-node work arrays of the tree solve
+  double *lw_d, *lw_r, *lw_dv;
   // constants
   double dt, q10dt;
   double ca_fm, ca_fr, ca_k;  // cahi: 1-exp(-dt/tau_m), 1-exp(-dt/tau_r), 1e4 tau_r / (2 F depth)

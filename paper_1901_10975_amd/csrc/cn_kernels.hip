@@ -186,6 +186,132 @@ __device__ __forceinline__ uint32_t bg_mask4(uint64_t seed, uint64_t key, uint64
          ((uint64_t)c3 < thresh ? 8u : 0u);
 }
 
+// Channel states of one compartment advanced with v (the update pending from the previous step, when `pend`), then
+// the currents and analytic conductances of its density mechanisms and IClamps at (v, states): rhs -= i, d += G
+// (Sec. 2, matrix assembly; Sec. 3.5, CONDUCTANCE). mf: the compartment's mechanism flags; pk: its counts word;
+// prm(col): one of its mechanism parameters; icl_of(): its first IClamp record.
+template <typename S, bool UNI, typename Prm, typename Icl>
+__device__ __forceinline__ void mech_terms(const KParams &p, uint32_t mf, uint32_t pk, Icl icl_of, int64_t n, double v,
+                                           bool pend, S q10dt, S sdt, S ca_fm, S ca_fr, S ca_k, StRec<S> &sr,
+                                           const lds_table *et, Prm prm, double &rhs, double &d) {
+  if (pend) {
+    if (mf & MF_HH) hh_advance<S>(v, q10dt, sr.m, sr.h, sr.n, et);
+    if (mf & MF_KM) km_advance<S>(v, sdt, sr.kn, et);
+    if (mf & MF_CAHI) cahi_advance<S>(v, ca_fm, ca_fr, ca_k, (S)prm(P_CA_G), sr.cm, sr.cai, et);
+  }
+  if (mf & MF_HH) {
+    const double gnab = prm(P_HH_GNA), gkb = prm(P_HH_GK), gl = prm(P_HH_GL), el = prm(P_HH_EL);
+    const double gna = (double)((S)gnab * (sr.m * sr.m * sr.m * sr.h));
+    const double gk = (double)((S)gkb * ((sr.n * sr.n) * (sr.n * sr.n)));
+    rhs -= gna * (v - 50.0) + gk * (v + 77.0) + gl * (v - el);
+    d += gna + gk + gl;
+  }
+  if (mf & MF_PAS) {
+    const double g = prm(P_PAS_G), e = prm(P_PAS_E);
+    rhs -= g * (v - e);
+    d += g;
+  }
+  if (mf & MF_KM) {
+    const double g = (double)((S)prm(P_KM_G) * sr.kn);
+    rhs -= g * (v + 77.0);
+    d += g;
+  }
+  if (mf & MF_CAHI) {
+    const double g = (double)((S)prm(P_CA_G) * (sr.cm * sr.cm));
+    rhs -= g * (v - 120.0);
+    d += g;
+  }
+  const int n_icl = (!UNI || p.has_icl) ? (int)((pk >> 16) & 0xFFu) : 0;
+  if (n_icl) {
+    const IclRec *ic = icl_of();
+    for (int c = 0; c < n_icl; ++c)
+      if (ic[c].on <= n && n < ic[c].off) rhs += ic[c].cur;
+  }
+}
+
+// The chunk's events on chip (Sec. 2, event delivery): the keys of this group's ring bucket for the interval and the
+// kicks due in the chunk, bitonic-sorted in LDS (key order is the delivery order), and in seg the first key of each
+// step of the interval. Called by all T threads of the group; ev, seg and misc are read only after a later barrier.
+// misc: [0] bucket keys, [1] the chunk's spike count (set to 0), [2] first kick, [3] kick count.
+template <int T>
+__device__ __forceinline__ void stage_events(const KParams &p, const GroupDesc &gd, int G, int t, int slot,
+                                             int64_t ival, int64_t n_begin, int64_t n_end, uint64_t *ev, int *seg,
+                                             int *misc) {
+  const int M = p.M;
+  if (t == 0) {
+    int lo = gd.kick_base, hi = gd.kick_base + gd.n_kick;
+    int a = lo, b = hi;  // first kick with step >= n_begin
+    while (a < b) {
+      const int mid = (a + b) >> 1;
+      if (p.kick_step[mid] < n_begin) a = mid + 1; else b = mid;
+    }
+    int c = a, e = hi;  // first kick with step >= n_end
+    while (c < e) {
+      const int mid = (c + e) >> 1;
+      if (p.kick_step[mid] < n_end) c = mid + 1; else e = mid;
+    }
+    int nbk = p.ev_cnt[(int64_t)slot * p.n_groups + G];
+    if (nbk > p.ev_cap) {
+      nbk = p.ev_cap;
+      atomicOr(&p.flags[FLAG_EV_OVERFLOW], 1);
+    }
+    int nk = c - a;
+    if (nbk + nk > p.ev_cap) {
+      nk = p.ev_cap - nbk;
+      atomicOr(&p.flags[FLAG_EV_OVERFLOW], 1);
+    }
+    misc[0] = nbk;
+    misc[1] = 0;  // spikes of this chunk
+    misc[2] = a;
+    misc[3] = nk;
+  }
+  __syncthreads();
+  const int nbk = misc[0], k0 = misc[2], nk = misc[3];
+  const int n_ev = nbk + nk;
+  int P = 1;
+  while (P < n_ev) P <<= 1;
+  {
+    const uint64_t *bucket = p.ev_key + ((int64_t)slot * p.n_groups + G) * p.ev_cap;
+    for (int i = t; i < P; i += T) {
+      uint64_t key = ~0ull;
+      if (i < nbk) {
+        key = bucket[i];
+      } else if (i < n_ev) {
+        const int kq = k0 + (i - nbk);
+        const uint64_t ss = (uint64_t)(p.kick_step[kq] - ival * M);
+        key = (ss << EV_STEP_SHIFT) | ((uint64_t)(uint32_t)p.kick_lsyn[kq] << EV_SYN_SHIFT) | (uint32_t)p.kick_id[kq];
+      }
+      ev[i] = key;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {  // bitonic sort of the keys
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < P; i += T) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = ev[i], y = ev[ixj];
+          const bool up = (i & k) == 0;
+          if (up ? (x > y) : (x < y)) {
+            ev[i] = y;
+            ev[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int s = t; s <= M; s += T) {  // first event of each step
+    const uint64_t target = (uint64_t)s << EV_STEP_SHIFT;
+    int a = 0, b = n_ev;
+    while (a < b) {
+      const int mid = (a + b) >> 1;
+      if (ev[mid] < target) a = mid + 1; else b = mid;
+    }
+    seg[s] = a;
+  }
+}
+
 // a node's own inputs to the elimination: a, b, children, and from the assembly d, rhs and dv (v at a root)
 struct TriIn {
   double a, b, d, r, dv;
@@ -316,77 +442,8 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     cst[C_CA_FM] = p.ca_fm;
     cst[C_CA_FR] = p.ca_fr;
     cst[C_CA_K] = p.ca_k;
-    int lo = gd.kick_base, hi = gd.kick_base + gd.n_kick;
-    int a = lo, b = hi;  // first kick with step >= n_begin
-    while (a < b) {
-      const int mid = (a + b) >> 1;
-      if (p.kick_step[mid] < n_begin) a = mid + 1; else b = mid;
-    }
-    int c = a, e = hi;  // first kick with step >= n_end
-    while (c < e) {
-      const int mid = (c + e) >> 1;
-      if (p.kick_step[mid] < n_end) c = mid + 1; else e = mid;
-    }
-    int nbk = p.ev_cnt[(int64_t)slot * p.n_groups + G];
-    if (nbk > p.ev_cap) {
-      nbk = p.ev_cap;
-      atomicOr(&p.flags[FLAG_EV_OVERFLOW], 1);
-    }
-    int nk = c - a;
-    if (nbk + nk > p.ev_cap) {
-      nk = p.ev_cap - nbk;
-      atomicOr(&p.flags[FLAG_EV_OVERFLOW], 1);
-    }
-    misc[0] = nbk;
-    misc[1] = 0;  // spikes of this chunk
-    misc[2] = a;
-    misc[3] = nk;
   }
-  __syncthreads();
-  const int nbk = misc[0], k0 = misc[2], nk = misc[3];
-  const int n_ev = nbk + nk;
-  int P = 1;
-  while (P < n_ev) P <<= 1;
-  {
-    const uint64_t *bucket = p.ev_key + ((int64_t)slot * p.n_groups + G) * p.ev_cap;
-    for (int i = t; i < P; i += T) {
-      uint64_t key = ~0ull;
-      if (i < nbk) {
-        key = bucket[i];
-      } else if (i < n_ev) {
-        const int kq = k0 + (i - nbk);
-        const uint64_t ss = (uint64_t)(p.kick_step[kq] - ival * M);
-        key = (ss << EV_STEP_SHIFT) | ((uint64_t)(uint32_t)p.kick_lsyn[kq] << EV_SYN_SHIFT) | (uint32_t)p.kick_id[kq];
-      }
-      ev[i] = key;
-    }
-  }
-  __syncthreads();
-  for (int k = 2; k <= P; k <<= 1) {  // bitonic sort of the keys
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = t; i < P; i += T) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t x = ev[i], y = ev[ixj];
-          const bool up = (i & k) == 0;
-          if (up ? (x > y) : (x < y)) {
-            ev[i] = y;
-            ev[ixj] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int s = t; s <= M; s += T) {  // first event of each step
-    const uint64_t target = (uint64_t)s << EV_STEP_SHIFT;
-    int a = 0, b = n_ev;
-    while (a < b) {
-      const int mid = (a + b) >> 1;
-      if (ev[mid] < target) a = mid + 1; else b = mid;
-    }
-    seg[s] = a;
-  }
+  stage_events<T>(p, gd, G, t, slot, ival, n_begin, n_end, ev, seg, misc);
 
   auto c_a = [&](int q) { return CL ? a_l[q] : p.nrec[nb + q].a; };
   auto c_b = [&](int q) { return CL ? b_l[q] : p.nrec[nb + q].b; };
@@ -558,40 +615,9 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         double rhs = 0.0, d = 0.0;
         // with one mechanism set on every compartment the flags are a kernel argument: uniform branches
         const uint32_t mf = UNI ? p.mf_uni : pk >> 24;
-        StRec<S> &sr = rs[j];
-        if (pend) {
-          if (mf & MF_HH) hh_advance<S>(v, q10dt, sr.m, sr.h, sr.n, etab3);
-          if (mf & MF_KM) km_advance<S>(v, sdt, sr.kn, etab3);
-          if (mf & MF_CAHI) cahi_advance<S>(v, ca_fm, ca_fr, ca_k, (S)prm(P_CA_G, i), sr.cm, sr.cai, etab3);
-        }
-        if (mf & MF_HH) {
-          const double gnab = prm(P_HH_GNA, i), gkb = prm(P_HH_GK, i), gl = prm(P_HH_GL, i), el = prm(P_HH_EL, i);
-          const double gna = (double)((S)gnab * (sr.m * sr.m * sr.m * sr.h));
-          const double gk = (double)((S)gkb * ((sr.n * sr.n) * (sr.n * sr.n)));
-          rhs -= gna * (v - 50.0) + gk * (v + 77.0) + gl * (v - el);
-          d += gna + gk + gl;
-        }
-        if (mf & MF_PAS) {
-          const double g = prm(P_PAS_G, i), e = prm(P_PAS_E, i);
-          rhs -= g * (v - e);
-          d += g;
-        }
-        if (mf & MF_KM) {
-          const double g = (double)((S)prm(P_KM_G, i) * sr.kn);
-          rhs -= g * (v + 77.0);
-          d += g;
-        }
-        if (mf & MF_CAHI) {
-          const double g = (double)((S)prm(P_CA_G, i) * (sr.cm * sr.cm));
-          rhs -= g * (v - 120.0);
-          d += g;
-        }
-        const int n_icl = (!UNI || p.has_icl) ? (int)((pk >> 16) & 0xFFu) : 0;
-        if (n_icl) {
-          const IclRec *ic = p.icl + gd.icl_base + p.nd_icl0[i];
-          for (int c = 0; c < n_icl; ++c)
-            if (ic[c].on <= n && n < ic[c].off) rhs += ic[c].cur;
-        }
+        mech_terms<S, UNI>(
+            p, mf, pk, [&]() { return p.icl + gd.icl_base + p.nd_icl0[i]; }, n, v, pend, q10dt, sdt, ca_fm, ca_fr,
+            ca_k, rs[j], etab3, [&](int col) { return prm(col, i); }, rhs, d);
         const int n_s = (int)(pk & 0xFFFFu);
         {
           if (staged) {
@@ -791,6 +817,155 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
   }
 }
 
+// ------------------------------------------------------------------------------------------------------------------
+// Interleaved layout, one lane per cell (the paper's one-cell-per-thread GPU ordering, Sec. 4.4): a group is up to 64
+// cells, one per lane of a single wave, whose compartments are interleaved in global memory: compartment k of lane j
+// sits at node_base + 64 k + j, in the caller's order (root first, parent before child), the group padded to its
+// largest cell with inert compartments (d = 1, no terms, parent the root). Each lane advances its own cell through
+// the chunk with no barrier: delivery and background events of its synapses, states, currents and assembly in one
+// pass over its compartments, then the serial elimination from the last compartment to the root and the
+// substitution back (Sec. 2, Gaussian elimination in the Hines order). Accesses are coalesced across the wave when
+// the 64 cells share the parent index of a compartment (identical cells), strided otherwise: the effect the paper
+// measures. The tree work arrays (d, rhs, dv) live in global memory. Threshold detection at the root, compacted in
+// cell order with a wave ballot.
+template <typename S, bool UNI>
+__global__ void __launch_bounds__(64) cn_lpc(const KParams p) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  uint64_t *ev = reinterpret_cast<uint64_t *>(lds + p.lds_ev_off);
+  int *seg = reinterpret_cast<int *>(lds + p.lds_seg_off);
+  uint8_t *bgm = reinterpret_cast<uint8_t *>(lds + p.lds_bg_off);
+  int *misc = reinterpret_cast<int *>(lds + p.lds_misc_off);
+  double *etab = reinterpret_cast<double *>(lds + p.lds_exp_off);
+  const lds_table *etab3 = (const lds_table *)etab;
+  const int G = blockIdx.x;
+  const int lane = threadIdx.x;
+  const GroupDesc gd = p.groups[G];
+  const int64_t n_begin = p.ctl[0];
+  const int64_t n_target = p.ctl[1];
+  const int64_t n_fresh = p.ctl[2];
+  const uint64_t seed = (uint64_t)p.ctl[3];
+  const int M = p.M;
+  const int64_t ival = n_begin / M;
+  const int64_t n_end = min(n_target, (ival + 1) * (int64_t)M);
+  if (n_end <= n_begin) return;
+  const int slot = (int)(ival % p.ring);
+  etab[lane] = p.exp_tab[lane];
+  stage_events<64>(p, gd, G, lane, slot, ival, n_begin, n_end, ev, seg, misc);
+  __syncthreads();
+
+  const bool act = lane < gd.n_cells;
+  const int KN = gd.n_levels;  // compartment slots per lane
+  const int64_t nb = gd.node_base + lane;
+  const int cb = gd.cell_base + lane;
+  const double theta = act ? p.cell_theta[cb] : 0.0;
+  StRec<S> *st = static_cast<StRec<S> *>(p.st);
+  const SynRec<S> *syn = static_cast<const SynRec<S> *>(p.syn) + gd.syn_base;
+  S *sg = static_cast<S *>(p.syn_g) + gd.syn_base;
+  double *V = p.v, *Dw = p.lw_d, *Rw = p.lw_r, *DVw = p.lw_dv;
+  auto prm = [&](int col, int64_t i) -> double { return UNI ? p.prm_s[col] : p.prm[col * p.n_nodes_total + i]; };
+  const S q10dt = (S)p.q10dt, sdt = (S)p.dt, ca_fm = (S)p.ca_fm, ca_fr = (S)p.ca_fr, ca_k = (S)p.ca_k;
+  double vold = act ? V[nb] : 0.0;
+  int nspk = 0;  // spikes of the chunk so far (uniform across the wave)
+  for (int64_t n = n_begin; n < n_end; ++n) {
+    const int s = (int)(n - ival * M);
+    const uint32_t bsh = (uint32_t)(n & 3);
+    // delivery: this cell's events of step n (a synapse belongs to the lane of its compartment), in key order
+    for (int e = seg[s]; e < seg[s + 1]; ++e) {
+      const uint64_t key = ev[e];
+      const int ls = (int)ev_syn(key);
+      if ((syn[ls].q & 63) != lane) continue;
+      const uint32_t id = (uint32_t)key & 0x7FFFFFFFu;
+      sg[ls] += (key & EV_KIND_NETCON) ? ld<S>(p.nc_w, id) : ld<S>(p.kick_w, id);
+    }
+    // background-event bits of the cell's synapses are drawn for a block of four steps
+    const bool draw = p.has_bg && (n == n_begin || (n & 3) == 0);
+    // states, currents and conductances, synapses, and the compartment's own matrix terms
+    const bool pend = n > n_fresh;
+    for (int k = 0; k < KN; ++k) {
+      const int64_t i = nb + 64 * (int64_t)k;
+      const NodeIdx nx = p.nidx[i];
+      const NodeRec nr = p.nrec[i];
+      const double v = V[i];
+      const uint32_t mf = UNI ? p.mf_uni : nx.pk >> 24;
+      double rhs = 0.0, d = 0.0;
+      if (mf & (MF_HH | MF_KM | MF_CAHI)) {
+        StRec<S> sr = st[i];
+        mech_terms<S, UNI>(
+            p, mf, nx.pk, [&]() { return p.icl + gd.icl_base + p.nd_icl0[i]; }, n, v, pend, q10dt, sdt, ca_fm, ca_fr,
+            ca_k, sr, etab3, [&](int col) { return prm(col, i); }, rhs, d);
+        st[i] = sr;
+      } else {
+        StRec<S> none{};
+        mech_terms<S, UNI>(
+            p, mf, nx.pk, [&]() { return p.icl + gd.icl_base + p.nd_icl0[i]; }, n, v, false, q10dt, sdt, ca_fm, ca_fr,
+            ca_k, none, etab3, [&](int col) { return prm(col, i); }, rhs, d);
+      }
+      const int n_s = (int)(nx.pk & 0xFFFFu);
+      for (int ls = nx.syn0; ls < nx.syn0 + n_s; ++ls) {
+        const SynRec<S> sy = syn[ls];
+        if (draw) bgm[ls] = (uint8_t)bg_mask4(seed, sy.key, (uint64_t)n >> 2, p.bg_thresh);
+        S g = sg[ls];
+        if (p.has_bg && ((bgm[ls] >> bsh) & 1u)) g += sy.wbg;
+        const double gs = sy.sa * (double)g;
+        rhs -= gs * (v - sy.e);
+        d += gs;
+        sg[ls] = g * sy.f;
+      }
+      d += nr.k;
+      double dv = v;  // the root carries its own potential
+      if (k > 0) {
+        dv = V[nb + 64 * (int64_t)nx.par] - v;
+        rhs -= nr.b * dv;
+      }
+      Dw[i] = d;
+      Rw[i] = rhs;
+      DVw[i] = dv;
+    }
+    // elimination, last compartment first: each compartment, final once its children (higher indices) are done,
+    // passes a (w + 1) and a (u - dv) to its parent's row (the parent's axial terms folded in)
+    for (int k = KN - 1; k >= 1; --k) {
+      const int64_t i = nb + 64 * (int64_t)k;
+      const double d = Dw[i], r = Rw[i], dv = DVw[i];
+      const NodeRec nr = p.nrec[i];
+      const int64_t ip = nb + 64 * (int64_t)p.nidx[i].par;
+      const double ri = rcp64<S>(d);
+      const double w = ri * nr.b, u = ri * r;
+      Dw[i] = w;
+      Rw[i] = u;
+      Dw[ip] -= fma(nr.a, w, nr.a);
+      Rw[ip] -= fma(nr.a, u, -(nr.a * dv));
+    }
+    // the root, threshold detection at it, and the substitution: x = u - w x_parent, v += x
+    double vnew = 0.0;
+    {
+      const double xs = Rw[nb] * rcp64<S>(Dw[nb]);
+      vnew = DVw[nb] + xs;
+      Rw[nb] = xs;
+      V[nb] = vnew;
+      if (act && !isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
+    }
+    for (int k = 1; k < KN; ++k) {
+      const int64_t i = nb + 64 * (int64_t)k;
+      const double x = Rw[i] - Dw[i] * Rw[nb + 64 * (int64_t)p.nidx[i].par];
+      Rw[i] = x;
+      V[i] += x;
+    }
+    const bool spk = act && vold < theta && theta <= vnew;
+    const uint64_t mask = __ballot(spk);
+    if (spk) {
+      const int idx = nspk + __popcll(mask & ((1ull << lane) - 1ull));
+      p.gsp_pack[gd.spk_base + idx] = lane | ((s + 1) << 16);
+      p.gsp_frac[gd.spk_base + idx] = (theta - vold) / (vnew - vold);
+    }
+    nspk += __popcll(mask);
+    vold = vnew;
+  }
+  if (lane == 0) {
+    p.gsp_cnt[G] = nspk;
+    if (n_end == (ival + 1) * (int64_t)M) p.ev_cnt[(int64_t)slot * p.n_groups + G] = 0;
+  }
+}
+
 // Spike record and fan-out of one chunk (Sec. 2 spike exchange, on one device): each spike walks its source cell's
 // NetCons and appends an event key to the ring slot of the interval it is due in. Slots of later intervals only, so
 // it never touches the slot the chunk just consumed (every delay is at least one interval).
@@ -942,6 +1117,21 @@ static IntervalFn interval_fn_s(int threads, int slots) {
 static IntervalFn interval_fn(bool fp32, int threads, int slots, bool uni) {
   if (uni) return fp32 ? interval_fn_s<float, true>(threads, slots) : interval_fn_s<double, true>(threads, slots);
   return fp32 ? interval_fn_s<float, false>(threads, slots) : interval_fn_s<double, false>(threads, slots);
+}
+
+static IntervalFn lpc_fn(bool fp32, bool uni) {
+  if (uni) return fp32 ? cn_lpc<float, true> : cn_lpc<double, true>;
+  return fp32 ? cn_lpc<float, false> : cn_lpc<double, false>;
+}
+
+hipError_t set_lpc_lds(bool fp32, bool uni, int lds_bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(lpc_fn(fp32, uni)),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+}
+
+hipError_t launch_lpc(const KParams &p, bool fp32, int lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(lpc_fn(fp32, p.prm == nullptr), dim3(p.n_groups), dim3(64), lds_bytes, st, p);
+  return hipGetLastError();
 }
 
 int interval_row_bytes(int nmax) { return lds_row_bytes(nmax); }

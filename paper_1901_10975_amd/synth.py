@@ -242,6 +242,50 @@ def cortex_200k(n_cells: int = 200000, seed: Optional[int] = None) -> Model:
                    10975 + 5 if seed is None else seed, 50.0, "cortex_200k")
 
 
+def ring_types(n_cells: int = 131072, n_comp: int = 83, cells_per_type: int = 1, ring_len: int = 128,
+               seed: Optional[int] = None, tstop: float = 10.0) -> Model:
+    """Rings of identical-size cells with a given number of identical cells per morphological type, the shape of the
+    paper's node-ordering experiment (Sec. 4.4: 131,072 cells of 83 compartments, random branching per type, 1 to 32
+    identical cells per type, 10 ms). Each type is a random recursive tree with its own geometry (a 20 x 20 um soma);
+    cell c has type
+    c // cells_per_type, so identical cells are adjacent. hh at the soma, pas elsewhere (a Ring-like cell: active
+    soma, passive dendrites); one ExpSyn (tau 2 ms, e 0 mV) at compartment 1, driven by the previous cell of its ring
+    of ring_len cells (weight 0.1 uS, delay 1 ms); the first cell of each ring is kicked at step 0."""
+    rng = np.random.default_rng(10975 + 6 if seed is None else seed)
+    n_types = -(-n_cells // cells_per_type)
+    # per type: a random recursive tree, dendrites of diameter U(0.5, 2) um and length U(10, 50) um, a 20 x 20 um soma
+    nt = n_types * n_comp
+    local = np.tile(np.arange(n_comp, dtype=np.int64), n_types)
+    t_parent = np.floor(rng.random(nt) * local).astype(np.int64)
+    t_parent[local == 0] = -1
+    diam = rng.uniform(0.5, 2.0, nt)
+    length = rng.uniform(10.0, 50.0, nt)
+    diam[local == 0] = 20.0
+    length[local == 0] = 20.0
+    t_area = np.pi * diam * length
+    half = (length / 2.0) / (np.pi * diam * diam / 4.0)
+    base = np.repeat(np.arange(n_types, dtype=np.int64) * n_comp, n_comp)
+    t_ri = 1e-2 * RA * (half + half[np.where(t_parent >= 0, t_parent + base, 0)])
+    t_ri[t_parent < 0] = 0.0
+    t_parent = t_parent.astype(np.int32)
+    typ = np.arange(n_cells, dtype=np.int64) // cells_per_type
+    idx = (typ[:, None] * n_comp + np.arange(n_comp, dtype=np.int64)[None, :]).ravel()
+    off = np.arange(n_cells + 1, dtype=np.int64) * n_comp
+    parent, area, ri = t_parent[idx].copy(), t_area[idx].copy(), t_ri[idx].copy()
+    soma = off[:-1].copy()
+    dend = np.setdiff1d(np.arange(n_cells * n_comp, dtype=np.int64), soma)
+    syn = MechTable(node=off[:-1] + 1, params={"tau": 2.0, "e": 0.0})
+    cells = np.arange(n_cells, dtype=np.int64)
+    ring0 = cells - cells % ring_len
+    nxt = ring0 + (cells - ring0 + 1) % np.minimum(ring_len, n_cells - ring0)
+    mechs = {"hh": MechTable(node=soma, params=dict(HH_PARAMS)), "pas": MechTable(node=dend, params=dict(PAS_PARAMS)),
+             "expsyn": syn}
+    kicks = np.arange(0, n_cells, ring_len, dtype=np.int64)
+    return _base(off, parent, area, ri, mechs, nc_src=cells.astype(np.int32), nc_syn=nxt, nc_weight=np.full(n_cells, 0.1),
+                 nc_delay=np.full(n_cells, 1.0), kick_step=np.zeros(kicks.size, np.int64), kick_syn=kicks,
+                 kick_weight=np.full(kicks.size, 0.1), tstop=tstop, name="ring_types")
+
+
 WORKLOADS = {"clamped_cells": clamped_cells, "ring_network": ring_network, "cortex_50k": cortex_50k,
              "cortex_200k": cortex_200k}
 

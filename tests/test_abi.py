@@ -96,19 +96,23 @@ def test_null_arguments_are_errors_not_crashes():
     L.cn_model_destroy(None)
 
 
-@pytest.mark.parametrize("name", ["clamped_cells", "ring_small", "cortex_50k_small", "cortex_200k_small", "edge"])
-def test_host_layout_checks_pass(name):
-    """the device layout (cell groups, level order, instance ranges, event targets) satisfies every invariant the
-    interval kernel indexes by; built and checked on the host only"""
+@pytest.mark.parametrize("layout", ["level", "interleaved"])
+@pytest.mark.parametrize("name", ["clamped_cells", "ring_small", "cortex_50k_small", "cortex_200k_small", "edge",
+                                  "ring_types"])
+def test_host_layout_checks_pass(name, layout):
+    """the device layout (cell groups, level or interleaved order, instance ranges, event targets) satisfies every
+    invariant the kernels index by; built and checked on the host only"""
     from tests.test_gpu_parity import _edge_model
     model = {"clamped_cells": lambda: synth.clamped_cells(),
              "ring_small": lambda: synth.ring_network(n_cells=100, n_comp=200),
              "cortex_50k_small": lambda: synth.cortex_50k(n_cells=3000),
              "cortex_200k_small": lambda: synth.cortex_200k(n_cells=300),
-             "edge": _edge_model}[name]()
-    e = cn.Engine(model, use_torch=False, validate_only=True)
+             "edge": _edge_model,
+             "ring_types": lambda: synth.ring_types(n_cells=700, cells_per_type=4)}[name]()
+    e = cn.Engine(model, use_torch=False, validate_only=True, layout=layout)
     info = e.info()
     assert info["n_comp"] == model.n_comp
+    assert info["layout"] == cn.LAYOUT[layout]
     assert info["max_group_nodes"] <= info["group_threads"] * info["group_slots"]
     assert info["n_groups"] >= 1
     with pytest.raises(cn.CnError) as err:

@@ -42,12 +42,15 @@ def test_autotune_times_candidates_and_caches(precision):
     say(f"  chose {t['group_threads']}x{t['group_slots']} fill {t['group_fill_pct']} at {t['interval_ms']:.3f} ms; "
         f"default {t['default_threads']}x{t['default_slots']} {t['default_ms']:.3f} ms; "
         f"{len(t['candidates'])} candidates")
-    assert not t["from_cache"] and len(t["candidates"]) >= 3
+    assert not t["from_cache"] and len(t["candidates"]) >= 4
     c0 = t["candidates"][0]
-    assert (c0["threads"], c0["slots"]) == (t["default_threads"], t["default_slots"])
+    assert (c0["layout"], c0["threads"], c0["slots"]) == ("level", t["default_threads"], t["default_slots"])
+    assert any(c["layout"] == "interleaved" for c in t["candidates"])
     assert t["interval_ms"] == min(c["interval_ms"] for c in t["candidates"]) > 0.0
     info = a.info()
-    assert (info["group_threads"], info["group_slots"]) == (t["group_threads"], t["group_slots"])
+    assert info["layout"] == (2 if t["layout"] == "interleaved" else 1)
+    if t["layout"] == "level":
+        assert (info["group_threads"], info["group_slots"]) == (t["group_threads"], t["group_slots"])
     b = _engine(m, precision=precision, autotune=True)
     assert b.tune["from_cache"] and b.tune["signature"] == t["signature"]
     assert (b.tune["group_threads"], b.tune["group_slots"]) == (t["group_threads"], t["group_slots"])
