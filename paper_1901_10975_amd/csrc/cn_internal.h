@@ -64,7 +64,7 @@ struct IclRec {
 };
 
 // constants the interval kernel keeps in LDS (indices into a small double table)
-enum { C_PRM = 0, C_Q10DT = 8, C_DT, C_CA_FM, C_CA_FR, C_CA_K, N_CST };
+enum { C_PRM = 0, C_Q10DT = 8, C_DT, C_CA_FM, C_CA_FR, C_CA_K, C_SEED, N_CST };
 
 struct GroupDesc {
   int64_t node_base;  // first node of the group in the node arrays

@@ -77,8 +77,8 @@ struct Math<float> {
   // for slow gates such as km with z near 3e-4); there the series z (1 - z/2 + z^2/6), whose first omitted term is
   // below 3e-9 relative, is selected without a branch.
   static __device__ __forceinline__ float omx(float z, const lds_table *) {
-    const float ser = z * (1.0f - z * (0.5f - z * (1.0f / 6.0f)));
-    return z < (1.0f / 64.0f) ? ser : 1.0f - __expf(-z);
+    const float e = __expf(-z);
+    return z < (1.0f / 64.0f) ? z * (1.0f - z * (0.5f - z * (1.0f / 6.0f))) : 1.0f - e;
   }
   // vtrap(x, y) = x / (exp(u) - 1) with u = x/y is y vser(u) near u = 0. In float, exp(u) - 1 loses ulp(1)/|u|
   // relative accuracy, so below |u| = 1/64 the series 1 - u/2 + u^2/12 (first omitted term u^4/720) is used.
@@ -419,8 +419,8 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
   const GroupDesc gd = p.groups[G];
   const int64_t n_begin = p.ctl[0];
   const int64_t n_target = p.ctl[1];
-  const int64_t n_fresh = p.ctl[2];  // the step whose channel states carry no pending update (0, or a restart)
-  const uint64_t seed = (uint64_t)p.ctl[3];
+  // the chunk's first step carries no pending state update when it is step 0 or the step of a restart (ctl[2])
+  const bool pend0 = n_begin > p.ctl[2];
   const int M = p.M;
   const int64_t ival = n_begin / M;
   const int64_t n_end = min(n_target, (ival + 1) * (int64_t)M);
@@ -442,6 +442,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     cst[C_CA_FM] = p.ca_fm;
     cst[C_CA_FR] = p.ca_fr;
     cst[C_CA_K] = p.ca_k;
+    reinterpret_cast<uint64_t *>(cst)[C_SEED] = (uint64_t)p.ctl[3];  // key of the background streams
   }
   stage_events<T>(p, gd, G, t, slot, ival, n_begin, n_end, ev, seg, misc);
 
@@ -524,6 +525,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     // background-event bits for a block of four steps (one Philox call gives four words)
     if (p.has_bg && (n == n_begin || (n & 3) == 0)) {
       const uint64_t blk = (uint64_t)n >> 2;
+      const uint64_t seed = reinterpret_cast<const uint64_t *>(cst)[C_SEED];
       for (int i = tid0; i < n_syn; i += stride) bgm[i] = (uint8_t)bg_mask4(seed, syn[i].key, blk, p.bg_thresh);
     }
     // A: delivery (Sec. 2, event-driven delivery step): one thread per synapse run, in key order
@@ -597,7 +599,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     // ---- C: states, currents, conductances and the compartment's own axial terms. Throughput work: it runs at
     // the lower wave priority, so that a co-resident group's latency-bound sweeps issue ahead of it.
     __builtin_amdgcn_s_setprio(0);
-    const bool pend = n > n_fresh;
+    const bool pend = n > n_begin || pend0;
     const S q10dt = (S)(KARG ? p.q10dt : cst[C_Q10DT]);
     const S sdt = (S)(KARG ? p.dt : cst[C_DT]);
     const S ca_fm = (S)(KARG ? p.ca_fm : cst[C_CA_FM]), ca_fr = (S)(KARG ? p.ca_fr : cst[C_CA_FR]),
