@@ -525,7 +525,9 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
     // background-event bits for a block of four steps (one Philox call gives four words)
     if (p.has_bg && (n == n_begin || (n & 3) == 0)) {
       const uint64_t blk = (uint64_t)n >> 2;
-      const uint64_t seed = reinterpret_cast<const uint64_t *>(cst)[C_SEED];
+      // the background key: from the control block in the FP64 kernels (a scalar load), from its LDS copy in the
+      // FP32-mechanism kernels, whose scalar registers are the scarcer resource
+      const uint64_t seed = KARG ? reinterpret_cast<const uint64_t *>(cst)[C_SEED] : (uint64_t)p.ctl[3];
       for (int i = tid0; i < n_syn; i += stride) bgm[i] = (uint8_t)bg_mask4(seed, syn[i].key, blk, p.bg_thresh);
     }
     // A: delivery (Sec. 2, event-driven delivery step): one thread per synapse run, in key order
