@@ -38,6 +38,7 @@ class OrcSpec(C.Structure):
         ("n_cahi", C.c_int64), ("cahi_node", _i64p), ("cahi_gbar", _dp),
         ("n_syn", C.c_int64), ("syn_node", _i64p), ("syn_tau", _dp), ("syn_e", _dp),
         ("n_icl", C.c_int64), ("icl_node", _i64p), ("icl_del", _dp), ("icl_dur", _dp), ("icl_amp", _dp),
+        ("n_gap", C.c_int64), ("gap_node", _i64p), ("gap_partner", _i64p), ("gap_g", _dp),
         ("n_nc", C.c_int64), ("nc_src", _i32p), ("nc_syn", _i64p), ("nc_w", _dp), ("nc_delay", _dp),
         ("threshold", _dp),
         ("n_kick", C.c_int64), ("kick_step", _i64p), ("kick_syn", _i64p), ("kick_w", _dp),
@@ -173,6 +174,11 @@ class OracleSim:
             setattr(s, nodef, _p(arr(t.nodes(n), np.int64), C.c_int64))
             for pname, field in cols:
                 setattr(s, field, _p(arr(t.column(pname, n), np.float64), C.c_double))
+        ng = int(getattr(model, "n_gap", 0))
+        s.n_gap = ng
+        s.gap_node = _p(arr(model.gap_node if ng else np.zeros(0), np.int64), C.c_int64)
+        s.gap_partner = _p(arr(model.gap_partner if ng else np.zeros(0), np.int64), C.c_int64)
+        s.gap_g = _p(arr(model.gap_g if ng else np.zeros(0), np.float64), C.c_double)
         s.n_nc = model.nc_src.shape[0]
         s.nc_src = _p(arr(model.nc_src, np.int32), C.c_int32)
         s.nc_syn = _p(arr(model.nc_syn, np.int64), C.c_int64)

@@ -186,6 +186,7 @@ struct orc_model {
   int64_t n_cahi; int64_t *cahi_node; double *ca_g, *ca_m, *ca_cai; csr_t cahi_c;
   int64_t n_syn; int64_t *syn_node; double *syn_e, *syn_f, *syn_g; csr_t syn_c;
   int64_t n_icl; int64_t *icl_node; double *icl_amp; int64_t *icl_on, *icl_off; csr_t icl_c;
+  int64_t n_gap; int64_t *gap_node, *gap_partner; double *gap_g, *gap_vp; csr_t gap_c;
   /* network */
   int64_t n_nc; int64_t *nc_syn; double *nc_w; int64_t *nc_D; int64_t *out_off, *out_nc;
   double *theta;
@@ -265,7 +266,8 @@ void orc_destroy(orc_model *m) {
                   m->hh_c.idx, m->pas_node, m->pas_g, m->pas_e, m->pas_c.off, m->pas_c.idx, m->km_node, m->km_g,
                   m->km_n, m->km_c.off, m->km_c.idx, m->cahi_node, m->ca_g, m->ca_m, m->ca_cai, m->cahi_c.off,
                   m->cahi_c.idx, m->syn_node, m->syn_e, m->syn_f, m->syn_g, m->syn_c.off, m->syn_c.idx,
-                  m->icl_node, m->icl_amp, m->icl_on, m->icl_off, m->icl_c.off, m->icl_c.idx, m->nc_syn, m->nc_w,
+                  m->icl_node, m->icl_amp, m->icl_on, m->icl_off, m->icl_c.off, m->icl_c.idx, m->gap_node,
+                  m->gap_partner, m->gap_g, m->gap_vp, m->gap_c.off, m->gap_c.idx, m->nc_syn, m->nc_w,
                   m->nc_D, m->out_off, m->out_nc, m->theta, m->kick_step, m->kick_syn, m->kick_w, m->pw, m->pkey,
                   m->pend_gid.v, m->pend_step.v, m->sp_gid.v, m->sp_step.v, m->sp_t, m->spiked, m->spike_t};
   for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
@@ -334,7 +336,9 @@ orc_model *orc_create(const orc_spec *s) {
   if (check_nodes(s->hh_node, s->n_hh, s->n_comp, 1, "hh") || check_nodes(s->pas_node, s->n_pas, s->n_comp, 1, "pas")
       || check_nodes(s->km_node, s->n_km, s->n_comp, 1, "km") || check_nodes(s->cahi_node, s->n_cahi, s->n_comp, 1, "cahi")
       || check_nodes(s->syn_node, s->n_syn, s->n_comp, 0, "expsyn")
-      || check_nodes(s->icl_node, s->n_icl, s->n_comp, 0, "iclamp"))
+      || check_nodes(s->icl_node, s->n_icl, s->n_comp, 0, "iclamp")
+      || check_nodes(s->gap_node, s->n_gap, s->n_comp, 0, "gap")
+      || check_nodes(s->gap_partner, s->n_gap, s->n_comp, 0, "gap partner"))
     goto fail;
   m->n_hh = s->n_hh;
   DUP(m->hh_node, s->hh_node, s->n_hh, int64_t);
@@ -387,7 +391,16 @@ orc_model *orc_create(const orc_spec *s) {
     m->icl_on[k] = (int64_t)ceil(s->icl_del[k] / s->dt - 0.5);
     m->icl_off[k] = (int64_t)ceil((s->icl_del[k] + s->icl_dur[k]) / s->dt - 0.5);
   }
-  if (build_csr(&m->hh_c, m->hh_node, m->n_hh, cell_of, m->n_cells) ||
+  m->n_gap = s->n_gap;
+  DUP(m->gap_node, s->gap_node, s->n_gap, int64_t);
+  DUP(m->gap_partner, s->gap_partner, s->n_gap, int64_t);
+  DUP(m->gap_g, s->gap_g, s->n_gap, double);
+  m->gap_vp = (double *)xcalloc((size_t)s->n_gap, sizeof(double));
+  if (s->n_gap && !m->gap_vp) goto nomem;
+  for (int64_t k = 0; k < s->n_gap; ++k)
+    if (!(s->gap_g[k] >= 0.0) || !isfinite(s->gap_g[k])) { set_err("gap conductance must be finite and >= 0"); goto fail; }
+  if (build_csr(&m->gap_c, m->gap_node, m->n_gap, cell_of, m->n_cells) ||
+      build_csr(&m->hh_c, m->hh_node, m->n_hh, cell_of, m->n_cells) ||
       build_csr(&m->pas_c, m->pas_node, m->n_pas, cell_of, m->n_cells) ||
       build_csr(&m->km_c, m->km_node, m->n_km, cell_of, m->n_cells) ||
       build_csr(&m->cahi_c, m->cahi_node, m->n_cahi, cell_of, m->n_cells) ||
@@ -544,6 +557,13 @@ static void cell_step(orc_model *m, int32_t cl, int64_t n) {
     rhs[i] -= 100.0 * m->syn_g[k] * (v[i] - m->syn_e[k]) / m->area[i];
     d[i] += 100.0 * m->syn_g[k] / m->area[i];
   }
+  /* half-gaps (reading R13): current g (v_i - v_partner) with the partner's potential from the start of the step,
+   * conductance g on the diagonal, both divided by area like every point process */
+  for (int64_t q = m->gap_c.off[cl]; q < m->gap_c.off[cl + 1]; ++q) {
+    int64_t k = m->gap_c.idx[q], i = m->gap_node[k];
+    rhs[i] -= 100.0 * m->gap_g[k] * (v[i] - m->gap_vp[k]) / m->area[i];
+    d[i] += 100.0 * m->gap_g[k] / m->area[i];
+  }
   /* capacitive term and axial coupling */
   for (int64_t i = i0; i < i0 + nn; ++i) d[i] += m->c[i];
   for (int64_t k = 1; k < nn; ++k) {
@@ -611,6 +631,8 @@ int orc_run(orc_model *m, int64_t n_target) {
   if (n_target < m->step) { set_err("cannot run backwards"); return -1; }
   for (int64_t n = m->step; n < n_target; ++n) {
     deliver(m, n);
+    /* the partners' potentials at the start of the step, before any cell advances */
+    for (int64_t k = 0; k < m->n_gap; ++k) m->gap_vp[k] = m->v[m->gap_partner[k]];
 #pragma omp parallel for num_threads(m->n_threads) schedule(dynamic, 16)
     for (int32_t cl = 0; cl < m->n_cells; ++cl) cell_step(m, cl, n);
     /* record spikes and queue their events in cell order */

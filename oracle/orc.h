@@ -45,6 +45,9 @@ typedef struct orc_spec {
   /* point processes */
   int64_t n_syn;  const int64_t *syn_node;  const double *syn_tau, *syn_e;
   int64_t n_icl;  const int64_t *icl_node;  const double *icl_del, *icl_dur, *icl_amp;
+  /* gap junctions, as half-gap instances: the current g (v_node - v_partner) nA at node, with the partner's
+   * potential taken at the start of the step (reading R13); a junction between two compartments is two instances */
+  int64_t n_gap;  const int64_t *gap_node, *gap_partner; const double *gap_g;
   /* network */
   int64_t n_nc; const int32_t *nc_src; const int64_t *nc_syn; const double *nc_w, *nc_delay;
   const double *threshold; /* [n_cells] mV */

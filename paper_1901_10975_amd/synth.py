@@ -90,6 +90,14 @@ class Model:
     tstop: float = 100.0
     name: str = ""
     poisson_key: Optional[np.ndarray] = None  # int64 [n_syn] background stream ids (None: instance index)
+    # gap junctions as half-gap instances: current g (v_node - v_partner) nA at gap_node
+    gap_node: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.int64))
+    gap_partner: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.int64))
+    gap_g: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))  # uS
+
+    @property
+    def n_gap(self) -> int:
+        return int(self.gap_node.shape[0])
 
     @property
     def n_comp(self) -> int:
@@ -286,6 +294,31 @@ def ring_types(n_cells: int = 131072, n_comp: int = 83, cells_per_type: int = 1,
                  kick_weight=np.full(kicks.size, 0.1), tstop=tstop, name="ring_types")
 
 
+def add_gap_junctions(m: Model, cluster: int = 2, per_pair: int = 1, g: float = 0.005,
+                      seed: Optional[int] = None) -> Model:
+    """Electrical coupling (gap junctions) within clusters of `cluster` consecutive cells: every pair of cells of a
+    cluster gets `per_pair` junctions between uniformly drawn compartments, conductance g uS, each junction as two
+    half-gap instances (one at each end). Returns the model with its gap arrays set."""
+    rng = np.random.default_rng(10975 + 7 if seed is None else seed)
+    off = m.cell_offset
+    sizes = np.diff(off)
+    nodes, partners = [], []
+    for c0 in range(0, m.n_cells, cluster):
+        members = list(range(c0, min(c0 + cluster, m.n_cells)))
+        for ia in range(len(members)):
+            for ib in range(ia + 1, len(members)):
+                a, b = members[ia], members[ib]
+                for _ in range(per_pair):
+                    na = off[a] + int(rng.integers(0, sizes[a]))
+                    nb = off[b] + int(rng.integers(0, sizes[b]))
+                    nodes += [na, nb]
+                    partners += [nb, na]
+    m.gap_node = np.asarray(nodes, np.int64)
+    m.gap_partner = np.asarray(partners, np.int64)
+    m.gap_g = np.full(m.gap_node.shape[0], float(g))
+    return m
+
+
 WORKLOADS = {"clamped_cells": clamped_cells, "ring_network": ring_network, "cortex_50k": cortex_50k,
              "cortex_200k": cortex_200k}
 
@@ -325,6 +358,7 @@ def subset_cells(m: Model, cells: np.ndarray) -> Model:
     pw = m.poisson_weight[syn_map >= 0] if m.poisson_weight.shape[0] else m.poisson_weight
     old_key = m.poisson_key if m.poisson_key is not None else np.arange(syn_map.shape[0], dtype=np.int64)
     pkey = old_key[syn_map >= 0]
+    gk = (node_map[m.gap_node] >= 0) & (node_map[m.gap_partner] >= 0) if m.n_gap else np.zeros(0, bool)
     return Model(
         n_cells=int(cells.shape[0]), cell_offset=off, parent=m.parent[old_nodes], area=m.area[old_nodes],
         ri=m.ri[old_nodes], cm=m.cm[old_nodes], v_init=m.v_init, celsius=m.celsius, mechs=mechs,
@@ -332,4 +366,5 @@ def subset_cells(m: Model, cells: np.ndarray) -> Model:
         nc_weight=m.nc_weight[nck], nc_delay=m.nc_delay[nck], threshold=m.threshold[cells],
         kick_step=m.kick_step[kk], kick_syn=syn_map[m.kick_syn[kk]], kick_weight=m.kick_weight[kk],
         poisson_rate_hz=m.poisson_rate_hz, poisson_weight=pw, seed=m.seed, dt=m.dt, tstop=m.tstop,
-        name=m.name + "-subset", poisson_key=pkey)
+        name=m.name + "-subset", poisson_key=pkey, gap_node=node_map[m.gap_node[gk]],
+        gap_partner=node_map[m.gap_partner[gk]], gap_g=m.gap_g[gk])

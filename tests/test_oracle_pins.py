@@ -760,3 +760,80 @@ def test_rounding_probe_moves_each_potential_by_at_most_one_ulp():
     up, down = np.nextafter(r, np.inf), np.nextafter(r, -np.inf)
     assert np.all((v == r) | (v == up) | (v == down))
     assert np.any(v == up) and np.any(v == down) and np.any(v == r)
+
+
+def _gap_pair(amp=0.05, g_gap=0.002, areas=(1000.0, 700.0), g=1e-4, e=-65.0):
+    """two single passive compartments (separate cells), a current clamp on the first, one gap junction between
+    them as two half-gap instances"""
+    m = TM.make([[-1], [-1]], np.array(areas), 0.0, {"pas": TM.pas(None, g, e), "iclamp": TM.iclamp([0], amp)})
+    m.gap_node = np.array([0, 1], np.int64)
+    m.gap_partner = np.array([1, 0], np.int64)
+    m.gap_g = np.array([g_gap, g_gap])
+    return m
+
+
+def test_gap_junction_steady_state_of_the_coupled_pair():
+    """Reading R13 at its fixed point: with v constant in time the explicit partner term and the implicit own term
+    agree, so the oracle settles at the steady state of the continuous coupled pair. Written in SI units in the
+    test: membrane conductance g_pas A (S/cm^2 x um^2), junction conductance G (uS), injected current I (nA):
+    g_pas A_a 1e-8 (v_a - e) + G 1e-6 (v_a - v_b) = I 1e-9 and the mirror equation without I."""
+    amp, G, (Aa, Ab), g, e = 0.05, 0.002, (1000.0, 700.0), 1e-4, -65.0
+    m = _gap_pair(amp, G, (Aa, Ab), g, e)
+    sim = O.OracleSim(m)
+    sim.run_to_step(200000)  # 5 s, many membrane time constants
+    gma, gmb = g * Aa * 1e-8, g * Ab * 1e-8  # S (1 um^2 = 1e-8 cm^2)
+    gj = G * 1e-6  # S
+    mat = np.array([[gma + gj, -gj], [-gj, gmb + gj]])
+    rhs = np.array([gma * e * 1e-3 + amp * 1e-9, gmb * e * 1e-3])  # A, with e in volts
+    va, vb = np.linalg.solve(mat, rhs) * 1e3  # mV
+    v = sim.v()
+    assert abs(v[0] - va) < 1e-9 and abs(v[1] - vb) < 1e-9, (v, va, vb)
+    assert v[1] > e + 1e-3  # the coupled cell is pulled up
+
+
+def test_gap_junction_one_step_is_semi_implicit():
+    """One step from a state with distinct potentials: each side's own potential implicit (the junction's
+    conductance on the diagonal), the partner's taken from the start of the step:
+    (c + g_pas + G') (v_a' - v_a) = -g_pas (v_a - e) - G' (v_a - v_b) + J, G' = 100 G / A, c = 1e-3 cm / dt."""
+    amp, G, (Aa, Ab), g, e, dt = 0.05, 0.002, (1000.0, 700.0), 1e-4, -65.0, 0.025
+    m = _gap_pair(amp, G, (Aa, Ab), g, e)
+    pre = O.OracleSim(m)
+    pre.run_to_step(37)
+    ck = pre.checkpoint()
+    ck["v"] = np.array([-40.0, -70.0])
+    sim = O.OracleSim(m)
+    sim.restore(ck)
+    sim.run_to_step(38)
+    va, vb = -40.0, -70.0
+    c = 1e-3 / dt
+    ga, gb = 100.0 * G / Aa, 100.0 * G / Ab
+    Ja = 100.0 * amp / Aa
+    da = (-g * (va - e) - ga * (va - vb) + Ja) / (c + g + ga)
+    db = (-g * (vb - e) - gb * (vb - va)) / (c + g + gb)
+    v = sim.v()
+    assert abs(v[0] - (va + da)) < 1e-12 and abs(v[1] - (vb + db)) < 1e-12, (v, va + da, vb + db)
+
+
+def test_gap_junction_symmetry_and_zero_conductance():
+    """two identical HH cells with identical input coupled symmetrically stay bitwise identical; a junction of zero
+    conductance leaves a network bitwise unchanged"""
+    cells = [TM.chain(5), TM.chain(5)]
+    mechs = {"hh": TM.hh(), "iclamp": TM.iclamp([0, 5], 0.3, dl=1.0)}
+    m = TM.make(cells, 800.0, 20.0, mechs)
+    m.gap_node = np.array([2, 7], np.int64)
+    m.gap_partner = np.array([7, 2], np.int64)
+    m.gap_g = np.array([0.01, 0.01])
+    sim = O.OracleSim(m)
+    sim.run(30.0)
+    v = sim.v()
+    assert np.array_equal(v[:5], v[5:])
+    g, s, _ = sim.spikes()
+    assert g.size >= 2 and np.array_equal(s[g == 0], s[g == 1])
+    r = synth.ring_network(n_cells=20, n_comp=15, seed=9)
+    a = O.OracleSim(r)
+    a.run(20.0)
+    r0 = synth.add_gap_junctions(synth.ring_network(n_cells=20, n_comp=15, seed=9), g=0.0)
+    assert r0.n_gap > 0
+    b = O.OracleSim(r0)
+    b.run(20.0)
+    assert np.array_equal(a.v(), b.v())
