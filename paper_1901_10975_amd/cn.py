@@ -53,7 +53,8 @@ class Network(C.Structure):
     _fields_ = [("n_netcon", C.c_int64), ("src_cell", _i32p), ("target_syn", _i64p), ("weight", _dp),
                 ("delay", _dp), ("threshold", _dp), ("threshold_scalar", C.c_double), ("n_kick", C.c_int64),
                 ("kick_step", _i64p), ("kick_syn", _i64p), ("kick_weight", _dp), ("poisson_rate_hz", C.c_double),
-                ("poisson_weight", _dp), ("seed", C.c_uint64), ("poisson_key", _i64p)]
+                ("poisson_weight", _dp), ("seed", C.c_uint64), ("poisson_key", _i64p), ("n_gap", C.c_int64),
+                ("gap_node", _i64p), ("gap_partner", _i64p), ("gap_g", _dp)]
 
 
 class Checkpoint(C.Structure):
@@ -208,6 +209,12 @@ def _describe(model: "synth.Model", keep: list):
                   int(model.seed) & 0xFFFFFFFFFFFFFFFF,
                   _ptr(arr(model.poisson_key, np.int64), C.c_int64) if model.poisson_key is not None
                   else _i64p())
+    ng = int(getattr(model, "n_gap", 0))
+    net.n_gap = ng
+    if ng:
+        net.gap_node = _ptr(arr(model.gap_node, np.int64), C.c_int64)
+        net.gap_partner = _ptr(arr(model.gap_partner, np.int64), C.c_int64)
+        net.gap_g = _ptr(arr(model.gap_g, np.float64), C.c_double)
     return topo, mtab, len(tables), net
 
 

@@ -114,6 +114,10 @@ struct cn_model {
   std::vector<double> pw;
   std::vector<int64_t> pkey;
   uint64_t seed = 0;
+  int64_t n_gap = 0;
+  std::vector<int64_t> gap_node, gap_partner;
+  std::vector<double> gap_g;
+  std::vector<int32_t> cell_cluster;  // cells joined by gap junctions share a cluster id (its smallest cell)
   cn_options opt{};
   bool fp32 = false;
 
@@ -325,6 +329,53 @@ void read_network(cn_model *m, const cn_network *net) {
     if (m->pkey[k] < 0) throw Err{CN_E_INVALID, "negative background stream id"};
   }
   m->seed = net->seed;
+  if (net->n_gap < 0 || net->n_gap >= (int64_t)INT32_MAX) throw Err{CN_E_INVALID, "bad gap-junction count"};
+  m->n_gap = net->n_gap;
+  if (m->n_gap > 0 && (!net->gap_node || !net->gap_partner || !net->gap_g))
+    throw Err{CN_E_INVALID, "gap-junction arrays missing"};
+  m->gap_node.assign(net->gap_node, net->gap_node + m->n_gap);
+  m->gap_partner.assign(net->gap_partner, net->gap_partner + m->n_gap);
+  m->gap_g.assign(net->gap_g, net->gap_g + m->n_gap);
+  for (int64_t k = 0; k < m->n_gap; ++k) {
+    if (m->gap_node[k] < 0 || m->gap_node[k] >= m->n_comp || m->gap_partner[k] < 0 ||
+        m->gap_partner[k] >= m->n_comp || m->gap_partner[k] == m->gap_node[k])
+      throw Err{CN_E_INVALID, "gap junction " + std::to_string(k) + ": compartment out of range or its own partner"};
+    if (!std::isfinite(m->gap_g[k]) || m->gap_g[k] < 0.0)
+      throw Err{CN_E_INVALID, "gap junction " + std::to_string(k) + ": conductance must be finite and >= 0"};
+  }
+}
+
+// Cells joined by gap junctions, found by union-find over cells: `cluster[c]` is the smallest cell of c's set.
+// Returns the compartments of the largest set (one cell's when there are no junctions). Entries out of range are
+// skipped here: they are refused where the network is read.
+int64_t join_cells(const int64_t *cell_off, int32_t n_cells, int64_t n_comp, int64_t n_gap, const int64_t *gn,
+                   const int64_t *gp, std::vector<int32_t> &cluster) {
+  cluster.resize(n_cells);
+  std::iota(cluster.begin(), cluster.end(), 0);
+  if (n_gap > 0 && gn && gp) {
+    std::vector<int32_t> cell_of(n_comp);
+    for (int32_t c = 0; c < n_cells; ++c)
+      for (int64_t i = cell_off[c]; i < cell_off[c + 1]; ++i) cell_of[i] = c;
+    auto find = [&](int32_t x) {
+      while (cluster[x] != x) x = cluster[x] = cluster[cluster[x]];
+      return x;
+    };
+    for (int64_t k = 0; k < n_gap; ++k) {
+      if (gn[k] < 0 || gn[k] >= n_comp || gp[k] < 0 || gp[k] >= n_comp) continue;
+      const int32_t a = find(cell_of[gn[k]]), b = find(cell_of[gp[k]]);
+      if (a != b) cluster[std::max(a, b)] = std::min(a, b);
+    }
+    for (int32_t c = 0; c < n_cells; ++c) cluster[c] = find(c);
+  }
+  std::vector<int64_t> size(n_cells, 0);
+  int64_t big = 0;
+  for (int32_t c = 0; c < n_cells; ++c) big = std::max(big, size[cluster[c]] += cell_off[c + 1] - cell_off[c]);
+  return big;
+}
+
+void gap_clusters(cn_model *m) {
+  join_cells(m->cell_off.data(), m->n_cells, m->n_comp, m->n_gap, m->gap_node.data(), m->gap_partner.data(),
+             m->cell_cluster);
 }
 
 // ---- device layout: cell groups (bin packing), level order, tables
@@ -450,8 +501,11 @@ void build_layout(cn_model *m) {
   const Table &syn = m->mech[CN_MECH_EXPSYN];
   for (int64_t k = 0; k < syn.n; ++k) syn_per_cell[cell_of[syn.node[k]]]++;
 
+  // the default shape holds the largest set of cells joined by gap junctions (one cell when there are none)
+  const int64_t max_unit = join_cells(m->cell_off.data(), m->n_cells, N, m->n_gap, m->gap_node.data(),
+                                      m->gap_partner.data(), m->cell_cluster);
   int T = m->opt.group_threads, K = m->opt.group_slots;
-  default_shape(N, max_cell, T, K);
+  default_shape(N, (int32_t)std::min<int64_t>(max_unit, INT32_MAX), T, K);
   if (!shape_compiled(T, K))
     throw Err{CN_E_INVALID, "no compiled cell-group shape " + std::to_string(T) + " x " + std::to_string(K)};
   if (T * K < max_cell) throw Err{CN_E_INVALID, "a cell has more compartments (" + std::to_string(max_cell) +
@@ -465,16 +519,37 @@ void build_layout(cn_model *m) {
   // synapses per group: up to two LDS rows, so that their terms can be staged on chip
   const int64_t syn_cap = 2 * m->nmax;
 
-  // best-fit decreasing on compartments, with a synapse cap per group
-  std::vector<int32_t> order(m->n_cells);
+  // best-fit decreasing on compartments, with a synapse cap per group. Cells joined by gap junctions are packed
+  // as one unit (their junctions read each other's potentials from the group's LDS), listed in cell order.
+  std::vector<std::vector<int32_t>> units;
+  {
+    std::vector<int32_t> unit_of(m->n_cells, -1);
+    for (int32_t c = 0; c < m->n_cells; ++c) {
+      const int32_t r = m->cell_cluster[c];
+      if (unit_of[r] < 0) {
+        unit_of[r] = (int32_t)units.size();
+        units.emplace_back();
+      }
+      units[unit_of[r]].push_back(c);
+    }
+  }
+  std::vector<int64_t> unit_size(units.size(), 0), unit_syn(units.size(), 0);
+  for (size_t u = 0; u < units.size(); ++u)
+    for (int32_t c : units[u]) {
+      unit_size[u] += cell_size[c];
+      unit_syn[u] += syn_per_cell[c];
+    }
+  std::vector<int32_t> order(units.size());
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cell_size[a] > cell_size[b]; });
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return unit_size[a] > unit_size[b]; });
   std::vector<std::vector<int32_t>> gcells;
   std::vector<int64_t> gnodes, gsyn;
   std::multimap<int64_t, int32_t> room;  // remaining capacity -> group
-  for (int32_t c : order) {
-    const int64_t sz = cell_size[c], sy = syn_per_cell[c];
-    if (sy >= MAX_GROUP_SYN) throw Err{CN_E_INVALID, "too many synapses on one cell"};
+  for (int32_t u : order) {
+    const int64_t sz = unit_size[u], sy = unit_syn[u];
+    if (sz > cap) throw Err{CN_E_INVALID, "cells joined by gap junctions hold " + std::to_string(sz) +
+                                              " compartments, more than one cell group (" + std::to_string(cap) + ")"};
+    if (sy >= MAX_GROUP_SYN) throw Err{CN_E_INVALID, "too many synapses on one cell group"};
     int32_t g = -1;
     int tries = 0;
     for (auto it = room.lower_bound(sz); it != room.end() && tries < 8; ++it, ++tries) {
@@ -490,7 +565,7 @@ void build_layout(cn_model *m) {
       gnodes.push_back(0);
       gsyn.push_back(0);
     }
-    gcells[g].push_back(c);
+    for (int32_t c : units[u]) gcells[g].push_back(c);
     gnodes[g] += sz;
     gsyn[g] += sy;
     const int64_t rem = cap - gnodes[g];
@@ -566,17 +641,48 @@ void build_layout(cn_model *m) {
 // identical cells given next to each other stay together), compartment k of lane j at node_base + 64 k + j
 void build_layout_lpc(cn_model *m) {
   const int64_t N = m->n_comp;
-  std::vector<int32_t> order(m->n_cells);
-  std::iota(order.begin(), order.end(), 0);
   auto size = [&](int32_t c) { return m->cell_off[c + 1] - m->cell_off[c]; };
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return size(a) > size(b); });
+  // units of cells that go to one group together: a cell, or the cells joined by gap junctions (in cell order);
+  // units ordered by their largest cell, and a group closed early when the next unit does not fit its lanes
+  gap_clusters(m);
+  std::vector<std::vector<int32_t>> units;
+  std::vector<int64_t> unit_max;
+  {
+    std::vector<int32_t> unit_of(m->n_cells, -1);
+    for (int32_t c = 0; c < m->n_cells; ++c) {
+      const int32_t r = m->cell_cluster[c];
+      if (unit_of[r] < 0) {
+        unit_of[r] = (int32_t)units.size();
+        units.emplace_back();
+        unit_max.push_back(0);
+      }
+      units[unit_of[r]].push_back(c);
+      unit_max[unit_of[r]] = std::max(unit_max[unit_of[r]], size(c));
+    }
+  }
+  std::vector<int32_t> uorder(units.size());
+  std::iota(uorder.begin(), uorder.end(), 0);
+  std::stable_sort(uorder.begin(), uorder.end(), [&](int32_t a, int32_t b) { return unit_max[a] > unit_max[b]; });
+  std::vector<int32_t> order;
+  std::vector<int32_t> gstart, gcount;  // each group's first entry in `order` and its cell count
+  order.reserve(m->n_cells);
+  for (int32_t u : uorder) {
+    const int32_t n = (int32_t)units[u].size();
+    if (n > 64) throw Err{CN_E_INVALID, "more than 64 cells joined by gap junctions (one interleaved group)"};
+    if (gstart.empty() || gcount.back() + n > 64) {
+      gstart.push_back((int32_t)order.size());
+      gcount.push_back(0);
+    }
+    for (int32_t c : units[u]) order.push_back(c);
+    gcount.back() += n;
+  }
   m->tree_par.assign(N, -1);
   m->cell_root.assign(m->n_cells, 0);
   for (int32_t c = 0; c < m->n_cells; ++c) {
     m->cell_root[c] = m->cell_off[c];
     for (int64_t i = m->cell_off[c] + 1; i < m->cell_off[c + 1]; ++i) m->tree_par[i] = m->cell_off[c] + m->parent[i];
   }
-  m->n_groups = (m->n_cells + 63) / 64;
+  m->n_groups = (int64_t)gstart.size();
   m->groups.assign(m->n_groups, GroupDesc{});
   m->cell_of_devcell.assign(order.begin(), order.end());
   m->lvl_start.clear();
@@ -584,8 +690,8 @@ void build_layout_lpc(cn_model *m) {
   int32_t max_kn = 0;
   for (int64_t g = 0; g < m->n_groups; ++g) {
     GroupDesc &gd = m->groups[g];
-    gd.cell_base = (int32_t)(64 * g);
-    gd.n_cells = (int32_t)std::min<int64_t>(64, m->n_cells - 64 * g);
+    gd.cell_base = gstart[g];
+    gd.n_cells = gcount[g];
     int32_t kn = 0;
     for (int32_t j = 0; j < gd.n_cells; ++j) kn = std::max<int32_t>(kn, (int32_t)size(order[gd.cell_base + j]));
     gd.node_base = base;
@@ -659,10 +765,12 @@ static void check_tree_layout(const cn_model *m, const std::vector<int32_t> &par
 // the interleaved layout: group g holds 64 lanes x n_levels slots from node_base on, slot 64 k + lane; lane j < n_cells
 // holds its cell's compartments at k = 0 .. size-1 (caller order, parent index below the compartment's), padding after
 static void check_lpc_layout(const cn_model *m, const std::vector<int32_t> &par) {
-  int64_t total = 0, real = 0;
+  int64_t total = 0, real = 0, cells = 0;
   for (int64_t g = 0; g < m->n_groups; ++g) {
     const GroupDesc &gd = m->groups[g];
     if (gd.node_base != total) layout_fail("node base");
+    if (gd.cell_base != cells) layout_fail("cell base");
+    cells += gd.n_cells;
     if (gd.n_cells < 1 || gd.n_cells > 64 || gd.n_levels < 1 || gd.n_nodes != 64 * gd.n_levels) layout_fail("group size");
     for (int32_t j = 0; j < 64; ++j) {
       int64_t size = 0;
@@ -683,7 +791,7 @@ static void check_lpc_layout(const cn_model *m, const std::vector<int32_t> &par)
     }
     total += gd.n_nodes;
   }
-  if (total != m->n_dev || real != m->n_comp) layout_fail("node total");
+  if (total != m->n_dev || real != m->n_comp || cells != m->n_cells) layout_fail("node total");
 }
 
 static void check_ranges(const cn_model *m, const std::vector<int2> &r, bool syn) {
@@ -889,6 +997,42 @@ static void build_tables(cn_model *m) {
   }
   check_ranges(m, nd_syn, true);
   check_ranges(m, nd_icl, false);
+  // half-gap junctions in device order (per node, ascending caller index). The partner sits in the same group
+  // (cells joined by a junction are packed together); its record holds the partner's group-local slot and the
+  // conductance per unit area of the junction's own compartment.
+  std::vector<int2> nd_gap(N, int2{0, 0});
+  p.gap = nullptr;
+  p.nd_gap0 = nullptr;
+  p.has_gap = m->n_gap > 0;
+  if (m->n_gap > 0) {
+    std::vector<int64_t> start(N + 1, 0), idx(m->n_gap);
+    for (int64_t k = 0; k < m->n_gap; ++k) start[m->dev_of_node[m->gap_node[k]] + 1]++;
+    for (int64_t dn = 0; dn < N; ++dn) start[dn + 1] += start[dn];
+    for (int64_t k = 0; k < m->n_gap; ++k) idx[start[m->dev_of_node[m->gap_node[k]]]++] = k;
+    std::vector<GapRec> gr(m->n_gap);
+    int64_t d = 0;
+    for (int64_t g = 0; g < m->n_groups; ++g) {
+      GroupDesc &gd = m->groups[g];
+      gd.gap_base = (int32_t)d;
+      const int64_t end = gd.node_base + gd.n_nodes, d0 = d;
+      while (d < m->n_gap && m->dev_of_node[m->gap_node[idx[d]]] < end) {
+        const int64_t k = idx[d], dn = m->dev_of_node[m->gap_node[k]], pd = m->dev_of_node[m->gap_partner[k]];
+        if (dn < gd.node_base || pd < gd.node_base || pd >= end) layout_fail("gap-junction partner outside its group");
+        if (nd_gap[dn].y == 0) nd_gap[dn].x = (int)(d - d0);
+        nd_gap[dn].y++;
+        gr[d] = GapRec{(int32_t)(pd - gd.node_base), 0, 100.0 * m->gap_g[k] / m->area[m->gap_node[k]]};
+        ++d;
+      }
+    }
+    if (d != m->n_gap) layout_fail("gap-junction order");
+    std::vector<int32_t> gap0(N, 0);
+    for (int64_t dn = 0; dn < N; ++dn) {
+      if (nd_gap[dn].y > MAX_NODE_GAP) throw Err{CN_E_INVALID, "more than 15 gap junctions on one compartment"};
+      gap0[dn] = nd_gap[dn].x;
+    }
+    p.gap = m->upload(gr);
+    p.nd_gap0 = m->upload(gap0);
+  }
   {
     std::vector<NodeIdx> nx(N);
     std::vector<int32_t> icl0(N, 0);
@@ -898,7 +1042,8 @@ static void build_tables(cn_model *m) {
       nx[dn].par = m->host_par[dn];
       nx[dn].ch = m->host_ch[dn];
       nx[dn].syn0 = nd_syn[dn].x;
-      nx[dn].pk = (uint32_t)nd_syn[dn].y | ((uint32_t)nd_icl[dn].y << 16) | ((uint32_t)m->host_mf[dn] << 24);
+      nx[dn].pk = (uint32_t)nd_syn[dn].y | ((uint32_t)nd_icl[dn].y << 16) | ((uint32_t)m->host_mf[dn] << 24) |
+                  ((uint32_t)nd_gap[dn].y << 28);
       icl0[dn] = nd_icl[dn].x;
     }
     p.nidx = m->upload(nx);
@@ -1644,6 +1789,7 @@ uint64_t tune_signature(const cn_topology *topo, const cn_mech_table *mechs, int
   }
   f.put(net ? net->n_netcon : (int64_t)0);
   f.put(net ? net->poisson_rate_hz : 0.0);
+  f.put(net ? net->n_gap : (int64_t)0);
   f.put(opt ? opt->precision : 0);
   f.put(opt ? opt->layout : 0);
   f.put(opt ? opt->event_capacity : 0);
@@ -1697,6 +1843,8 @@ int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_m
   if (opt && opt->validate_only) return fail(CN_E_STATE, "autotuning needs a device");
   for (int32_t c = 0; c < topo->n_cells; ++c)
     if (topo->cell_offset[c + 1] <= topo->cell_offset[c]) return fail(CN_E_INVALID, "cell_offset must be strictly increasing");
+  if (topo->cell_offset[0] != 0 || topo->cell_offset[topo->n_cells] != topo->n_comp)
+    return fail(CN_E_INVALID, "cell_offset must run from 0 to n_comp");
   cn_options base{};
   if (opt) base = *opt;
   const uint64_t sig = tune_signature(topo, mechs, n_mechs, net, &base, dt);
@@ -1713,6 +1861,12 @@ int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_m
   int32_t max_cell = 0;
   for (int32_t c = 0; c < topo->n_cells; ++c)
     max_cell = std::max<int32_t>(max_cell, (int32_t)(topo->cell_offset[c + 1] - topo->cell_offset[c]));
+  {
+    std::vector<int32_t> cl;
+    const int64_t u = join_cells(topo->cell_offset, topo->n_cells, topo->n_comp, net ? net->n_gap : 0,
+                                 net ? net->gap_node : nullptr, net ? net->gap_partner : nullptr, cl);
+    max_cell = (int32_t)std::min<int64_t>(std::max<int64_t>(max_cell, u), INT32_MAX);
+  }
   int dT = 0, dK = 0;
   default_shape(topo->n_comp, max_cell, dT, dK);
   // candidates: the default first; for each thread count, the smallest slot count that holds the largest cell and

@@ -24,6 +24,7 @@ constexpr int MAX_INTERVAL = 1023;
 constexpr int64_t MAX_GROUP_SYN = (int64_t)EV_SYN_MASK + 1;
 constexpr int MAX_NODE_SYN = 0xFFFF;  // synapses on one compartment
 constexpr int MAX_NODE_ICL = 0xFF;    // IClamps on one compartment
+constexpr int MAX_NODE_GAP = 0xF;     // half-gap junctions on one compartment
 
 // per-node constants of the tree matrix (S/cm^2): a (row parent, column node), b (row node, column parent),
 // k = 1e-3 cm/dt - b (capacitance and the node's own axial term on the diagonal), sa = 100/area (point processes)
@@ -31,7 +32,7 @@ struct NodeRec {
   double a, b, k, sa;
 };
 // per-node indices: parent (group-local, -1 at roots), children (first | count << 16, group-local), first synapse
-// (group-local) and pk = synapse count | IClamp count << 16 | mechanism flags << 24
+// (group-local) and pk = synapse count | IClamp count << 16 | mechanism flags << 24 | half-gap count << 28
 struct NodeIdx {
   int32_t par;
   uint32_t ch;
@@ -56,6 +57,12 @@ template <typename S>
 struct StRec {
   S m, h, n, kn, cm, cai;
 };
+// half-gap record (device order): the partner compartment (group-local node) and 100 g / area (S/cm^2)
+struct GapRec {
+  int32_t q;
+  int32_t pad;
+  double gs;
+};
 // IClamp record (device order): on for steps on <= n < off, current density 100 amp / area (mA/cm^2)
 struct IclRec {
   int64_t on, off;
@@ -71,7 +78,7 @@ struct GroupDesc {
   int64_t syn_base;   // first synapse of the group
   int32_t n_nodes, n_levels, lvl_base, n_cells;
   int32_t cell_base, n_syn, kick_base, n_kick;
-  int32_t spk_base, icl_base, pad0, pad1;
+  int32_t spk_base, icl_base, gap_base, pad1;
 };
 
 // non-uniform density-mechanism parameters, columns of the per-node parameter table
@@ -88,12 +95,15 @@ struct KParams {
   int32_t has_bg;
   uint32_t mf_uni;   // the density-mechanism flags every compartment carries (kernels for uniform models)
   int32_t has_icl;   // any IClamp in the model
+  int32_t has_gap;   // any gap junction in the model
   int32_t lds_ev_off, lds_seg_off, lds_lvl_off, lds_bg_off, lds_cell_off, lds_misc_off, lds_cst_off, lds_exp_off;
   const double *exp_tab;   // 2^(j/64), j = 0..63
   // node tables (device order)
   const NodeRec *nrec;
   const NodeIdx *nidx;
   const int32_t *nd_icl0;  // group-local first IClamp of each node
+  const int32_t *nd_gap0;  // group-local first half-gap of each node
+  const GapRec *gap;       // half-gaps (device order)
   double *v;               // membrane potential between chunks
   void *st;                // StRec<double> or StRec<float> per node
   int64_t n_nodes_total;

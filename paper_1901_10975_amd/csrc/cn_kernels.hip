@@ -618,7 +618,7 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
         const double v = V_l[q];
         double rhs = 0.0, d = 0.0;
         // with one mechanism set on every compartment the flags are a kernel argument: uniform branches
-        const uint32_t mf = UNI ? p.mf_uni : pk >> 24;
+        const uint32_t mf = UNI ? p.mf_uni : (pk >> 24) & 0xFu;
         mech_terms<S, UNI>(
             p, mf, pk, [&]() { return p.icl + gd.icl_base + p.nd_icl0[i]; }, n, v, pend, q10dt, sdt, ca_fm, ca_fr,
             ca_k, rs[j], etab3, [&](int col) { return prm(col, i); }, rhs, d);
@@ -649,6 +649,15 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
               d += gs;
               sg[ls] = g * sy.f;
             }
+          }
+        }
+        // half-gap junctions (reading R13): the partner's potential from the start of the step, still in V_l
+        const int n_gap = (!UNI || p.has_gap) ? (int)(pk >> 28) : 0;
+        if (n_gap) {
+          const GapRec *gr = p.gap + gd.gap_base + p.nd_gap0[i];
+          for (int c = 0; c < n_gap; ++c) {
+            rhs -= gr[c].gs * (v - V_l[gr[c].q]);
+            d += gr[c].gs;
           }
         }
         d += c_k(q);
@@ -890,7 +899,7 @@ __global__ void __launch_bounds__(64) cn_lpc(const KParams p) {
       const NodeIdx nx = p.nidx[i];
       const NodeRec nr = p.nrec[i];
       const double v = V[i];
-      const uint32_t mf = UNI ? p.mf_uni : nx.pk >> 24;
+      const uint32_t mf = UNI ? p.mf_uni : (nx.pk >> 24) & 0xFu;
       double rhs = 0.0, d = 0.0;
       if (mf & (MF_HH | MF_KM | MF_CAHI)) {
         StRec<S> sr = st[i];
@@ -914,6 +923,16 @@ __global__ void __launch_bounds__(64) cn_lpc(const KParams p) {
         rhs -= gs * (v - sy.e);
         d += gs;
         sg[ls] = g * sy.f;
+      }
+      // half-gap junctions: the partner is a compartment of this wave's cells, whose potential is still the one at
+      // the start of the step (every lane updates potentials only in the substitution below)
+      const int n_gap = (!UNI || p.has_gap) ? (int)(nx.pk >> 28) : 0;
+      if (n_gap) {
+        const GapRec *gr = p.gap + gd.gap_base + p.nd_gap0[i];
+        for (int c = 0; c < n_gap; ++c) {
+          rhs -= gr[c].gs * (v - V[gd.node_base + gr[c].q]);
+          d += gr[c].gs;
+        }
       }
       d += nr.k;
       double dv = v;  // the root carries its own potential

@@ -98,7 +98,7 @@ def test_null_arguments_are_errors_not_crashes():
 
 @pytest.mark.parametrize("layout", ["level", "interleaved"])
 @pytest.mark.parametrize("name", ["clamped_cells", "ring_small", "cortex_50k_small", "cortex_200k_small", "edge",
-                                  "ring_types"])
+                                  "ring_types", "ring_gap"])
 def test_host_layout_checks_pass(name, layout):
     """the device layout (cell groups, level or interleaved order, instance ranges, event targets) satisfies every
     invariant the kernels index by; built and checked on the host only"""
@@ -108,7 +108,9 @@ def test_host_layout_checks_pass(name, layout):
              "cortex_50k_small": lambda: synth.cortex_50k(n_cells=3000),
              "cortex_200k_small": lambda: synth.cortex_200k(n_cells=300),
              "edge": _edge_model,
-             "ring_types": lambda: synth.ring_types(n_cells=700, cells_per_type=4)}[name]()
+             "ring_types": lambda: synth.ring_types(n_cells=700, cells_per_type=4),
+             "ring_gap": lambda: synth.add_gap_junctions(synth.ring_network(n_cells=130, n_comp=60), cluster=5,
+                                                         per_pair=2)}[name]()
     e = cn.Engine(model, use_torch=False, validate_only=True, layout=layout)
     info = e.info()
     assert info["n_comp"] == model.n_comp
@@ -131,3 +133,56 @@ def test_restore_and_seed_argument_checks():
     with pytest.raises(cn.CnError) as err:
         e.restore(ck)
     assert err.value.code == cn.CN_E_STATE
+
+
+def _gapped(**kw):
+    return synth.add_gap_junctions(synth.ring_network(n_cells=12, n_comp=30), **kw)
+
+
+def test_rejects_bad_gap_junctions():
+    """a half-gap names two distinct compartments in range and a finite conductance >= 0"""
+    for field, k, val, what in (("gap_node", 0, -1, "range"), ("gap_partner", 1, 10 ** 6, "range"),
+                                ("gap_g", 2, -0.1, "conductance"), ("gap_g", 0, np.nan, "conductance")):
+        m = _gapped()
+        getattr(m, field)[k] = val
+        assert what in _expect_invalid(m)
+    m = _gapped()
+    m.gap_partner[0] = m.gap_node[0]
+    assert "own partner" in _expect_invalid(m)
+
+
+def test_rejects_gap_clusters_larger_than_a_group():
+    """cells joined by junctions share a cell group: a cluster larger than the group, or more than 64 cells for the
+    interleaved layout, or more than 15 half-gaps on one compartment, is refused"""
+    m = _gapped(cluster=12)  # 360 compartments joined
+    assert "gap junctions" in _expect_invalid(m, group_threads=128, group_slots=2, validate_only=True)
+    m = synth.add_gap_junctions(synth.ring_network(n_cells=70, n_comp=3), cluster=70, per_pair=0)
+    m.gap_node = np.arange(69, dtype=np.int64) * 3
+    m.gap_partner = m.gap_node + 3
+    m.gap_g = np.full(69, 0.001)
+    assert "64 cells" in _expect_invalid(m, layout="interleaved", validate_only=True)
+    m = _gapped()
+    m.gap_node = np.zeros(16, np.int64)
+    m.gap_partner = np.arange(16, dtype=np.int64) + 30
+    m.gap_g = np.full(16, 0.001)
+    assert "15 gap" in _expect_invalid(m, validate_only=True)
+    m = _gapped(cluster=12)
+    info = cn.Engine(m, use_torch=False, validate_only=True).info()
+    assert info["n_groups"] == 1 and info["group_threads"] * info["group_slots"] >= 360  # default shape holds it
+
+
+@pytest.mark.parametrize("layout", ["level", "interleaved"])
+def test_gap_clusters_share_a_group(layout):
+    """the packing keeps every junction's two ends in one group (the host layout check refuses anything else),
+    with clusters of several sizes"""
+    for cluster in (2, 7):
+        m = synth.add_gap_junctions(synth.ring_network(n_cells=200, n_comp=40), cluster=cluster)
+        e = cn.Engine(m, use_torch=False, validate_only=True, layout=layout)
+        assert e.info()["n_comp"] == m.n_comp
+    # chains of 64 cells (the most one interleaved group holds), junctions between neighbours' somata
+    m = synth.ring_network(n_cells=200, n_comp=3)
+    a = np.array([c for c in range(199) if c % 64 != 63], np.int64) * 3
+    m.gap_node, m.gap_partner = np.concatenate([a, a + 3]), np.concatenate([a + 3, a])
+    m.gap_g = np.full(m.gap_node.shape[0], 0.002)
+    e = cn.Engine(m, use_torch=False, validate_only=True, layout=layout)
+    assert e.info()["n_comp"] == m.n_comp
