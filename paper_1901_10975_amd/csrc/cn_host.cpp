@@ -933,11 +933,11 @@ static void build_tables(cn_model *m) {
       p.prm_s[c] = tb.present ? tb.p[cols[c][1]].s : 0.0;
       if (tb.present && !tb.p[cols[c][1]].uniform) any = true;
     }
-    // the uniform kernels also need one mechanism set on every compartment; otherwise the parameters go to the
-    // table as well
+    // the uniform kernels also need one mechanism set on every compartment and carry no gap-junction terms;
+    // otherwise the parameters go to the table as well
     const bool same_mechs = N == 0 || std::all_of(mf.begin(), mf.end(), [&](uint8_t x) { return x == mf[0]; });
     p.mf_uni = N ? mf[0] : 0;
-    if (!same_mechs) any = true;
+    if (!same_mechs || m->n_gap > 0) any = true;
     p.prm = nullptr;
     if (any) {
       std::vector<double> t(N_PRM * (size_t)N, 0.0);
@@ -1003,7 +1003,6 @@ static void build_tables(cn_model *m) {
   std::vector<int2> nd_gap(N, int2{0, 0});
   p.gap = nullptr;
   p.nd_gap0 = nullptr;
-  p.has_gap = m->n_gap > 0;
   if (m->n_gap > 0) {
     std::vector<int64_t> start(N + 1, 0), idx(m->n_gap);
     for (int64_t k = 0; k < m->n_gap; ++k) start[m->dev_of_node[m->gap_node[k]] + 1]++;

@@ -382,12 +382,13 @@ constexpr bool const_in_lds(int nmax) { return nmax <= 2048; }
 // bytes of the node rows: two 32-bit rows of nmax and eight double rows of nmax + 1 entries, or five double rows
 constexpr int lds_row_bytes(int nmax) { return const_in_lds(nmax) ? 8 * nmax + 64 * (nmax + 1) : 40 * (nmax + 1); }
 // waves per SIMD the register budget is sized for: more register slots per thread keep more compartments on chip
-constexpr int waves_for_slots(int K) { return K <= 1 ? 4 : (K == 2 ? 3 : (K == 4 ? 2 : 1)); }
+// (a group of 512 threads puts two waves on every SIMD, so two co-resident groups need four)
+constexpr int waves_for_shape(int T, int K) { return K <= 1 ? 4 : (K == 2 ? (T >= 512 ? 4 : 3) : (K == 4 ? 2 : 1)); }
 
 // UNI: every compartment carries the same density mechanisms (flags in mf_uni) and every parameter is uniform
 // (read from the LDS constants, not the per-node table)
 template <int T, int K, typename S, bool UNI>
-__global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KParams p) {
+__global__ void __launch_bounds__(T, waves_for_shape(T, K)) cn_interval(const KParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int NMAX = T * K;
   constexpr bool CL = const_in_lds(NMAX);
@@ -651,8 +652,9 @@ __global__ void __launch_bounds__(T, waves_for_slots(K)) cn_interval(const KPara
             }
           }
         }
-        // half-gap junctions (reading R13): the partner's potential from the start of the step, still in V_l
-        const int n_gap = (!UNI || p.has_gap) ? (int)(pk >> 28) : 0;
+        // half-gap junctions (reading R13): the partner's potential from the start of the step, still in V_l (a
+        // model with junctions runs the general kernels: the uniform ones keep their registers for the rest)
+        const int n_gap = UNI ? 0 : (int)(pk >> 28);
         if (n_gap) {
           const GapRec *gr = p.gap + gd.gap_base + p.nd_gap0[i];
           for (int c = 0; c < n_gap; ++c) {
@@ -926,7 +928,7 @@ __global__ void __launch_bounds__(64) cn_lpc(const KParams p) {
       }
       // half-gap junctions: the partner is a compartment of this wave's cells, whose potential is still the one at
       // the start of the step (every lane updates potentials only in the substitution below)
-      const int n_gap = (!UNI || p.has_gap) ? (int)(nx.pk >> 28) : 0;
+      const int n_gap = UNI ? 0 : (int)(nx.pk >> 28);
       if (n_gap) {
         const GapRec *gr = p.gap + gd.gap_base + p.nd_gap0[i];
         for (int c = 0; c < n_gap; ++c) {
