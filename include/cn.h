@@ -271,6 +271,8 @@ typedef struct cn_info {
   double dt;
   int32_t layout; /* CN_LAYOUT_LEVEL or CN_LAYOUT_INTERLEAVED; for INTERLEAVED, group_threads is 64 (one lane per
                      cell) and group_slots the largest cell's compartment count */
+  int32_t groups_per_cu; /* cell groups the interval kernel keeps co-resident on one compute unit (its registers,
+                            LDS and waves allow); 0 before the first cn_run fixes dt */
 } cn_info;
 int cn_model_info(const cn_model *m, cn_info *out);
 

@@ -93,7 +93,7 @@ class Info(C.Structure):
                 ("interval_steps", C.c_int32), ("group_threads", C.c_int32), ("group_slots", C.c_int32),
                 ("max_group_nodes", C.c_int32), ("max_levels", C.c_int32), ("ring_slots", C.c_int32),
                 ("event_capacity", C.c_int32), ("precision", C.c_int32), ("lds_bytes", C.c_int32),
-                ("dt", C.c_double), ("layout", C.c_int32)]
+                ("dt", C.c_double), ("layout", C.c_int32), ("groups_per_cu", C.c_int32)]
 
 
 _lib = None

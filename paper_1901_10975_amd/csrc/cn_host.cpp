@@ -28,6 +28,8 @@ hipError_t launch_interval(const KParams &p, bool fp32, int threads, int slots, 
 hipError_t set_interval_lds(bool fp32, int threads, int slots, bool uni, int lds_bytes);
 hipError_t launch_lpc(const KParams &p, bool fp32, int lds_bytes, hipStream_t st);
 hipError_t set_lpc_lds(bool fp32, bool uni, int lds_bytes);
+hipError_t interval_groups_per_cu(bool fp32, int threads, int slots, bool uni, int lds_bytes, int *n);
+hipError_t lpc_groups_per_cu(bool fp32, bool uni, int lds_bytes, int *n);
 int interval_row_bytes(int nmax);
 hipError_t launch_advance(int64_t *ctl, int32_t M, hipStream_t st);
 hipError_t launch_fanout(const KParams &p, hipStream_t st);
@@ -156,6 +158,7 @@ struct cn_model {
   int64_t device_bytes = 0;
   KParams kp{};
   int lds_bytes = 0;
+  int groups_per_cu = 0;  // co-resident groups on one CU (registers, LDS, waves), from the occupancy query
   int32_t spk_total = 0;
   int32_t drain_every = 1;
   hipGraph_t graph = nullptr;
@@ -1323,8 +1326,13 @@ static void prepare_dt(cn_model *m, double dt) {
   if (m->lds_bytes > 160 * 1024)
     throw Err{CN_E_INVALID, "cell groups need " + std::to_string(m->lds_bytes) + " bytes of LDS (event_capacity "
                                 "or synapses per group too large)"};
-  if (m->lpc) HIPCHK(set_lpc_lds(m->fp32, p.prm == nullptr, m->lds_bytes));
-  else HIPCHK(set_interval_lds(m->fp32, m->threads, m->slots, p.prm == nullptr, m->lds_bytes));
+  if (m->lpc) {
+    HIPCHK(set_lpc_lds(m->fp32, p.prm == nullptr, m->lds_bytes));
+    HIPCHK(lpc_groups_per_cu(m->fp32, p.prm == nullptr, m->lds_bytes, &m->groups_per_cu));
+  } else {
+    HIPCHK(set_interval_lds(m->fp32, m->threads, m->slots, p.prm == nullptr, m->lds_bytes));
+    HIPCHK(interval_groups_per_cu(m->fp32, m->threads, m->slots, p.prm == nullptr, m->lds_bytes, &m->groups_per_cu));
+  }
   HIPCHK(hipStreamSynchronize(m->stream));
   if (m->opt.use_graph) {
     HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
@@ -1963,6 +1971,7 @@ int cn_model_info(const cn_model *m, cn_info *o) {
   o->lds_bytes = m->lds_bytes;
   o->dt = m->dt;
   o->layout = m->lpc ? CN_LAYOUT_INTERLEAVED : CN_LAYOUT_LEVEL;
+  o->groups_per_cu = m->dt_fixed ? m->groups_per_cu : 0;
   return CN_OK;
 }
 

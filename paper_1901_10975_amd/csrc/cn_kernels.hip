@@ -381,14 +381,19 @@ __device__ __forceinline__ void tri_node(int q, const TriIn &x, int zero8, doubl
 constexpr bool const_in_lds(int nmax) { return nmax <= 2048; }
 // bytes of the node rows: two 32-bit rows of nmax and eight double rows of nmax + 1 entries, or five double rows
 constexpr int lds_row_bytes(int nmax) { return const_in_lds(nmax) ? 8 * nmax + 64 * (nmax + 1) : 40 * (nmax + 1); }
-// waves per SIMD the register budget is sized for: more register slots per thread keep more compartments on chip
-// (a group of 512 threads puts two waves on every SIMD, so two co-resident groups need four)
-constexpr int waves_for_shape(int T, int K) { return K <= 1 ? 4 : (K == 2 ? (T >= 512 ? 4 : 3) : (K == 4 ? 2 : 1)); }
+// Waves per SIMD the register budget is sized for: more register slots per thread keep more compartments on chip.
+// A group of 512 threads puts two waves on every SIMD, so two co-resident groups need four. The general 512 x 2
+// kernels are held to four (a few registers spill); the uniform ones fit in 128 registers under a bound of three,
+// whose schedule is measured 7-10 % faster than the one compiled for four. cn_model_info reports the groups that
+// are co-resident on a CU, so a kernel that outgrows 128 registers shows up there.
+constexpr int waves_for_shape(int T, int K, bool uni) {
+  return K <= 1 ? 4 : (K == 2 ? (T >= 512 && !uni ? 4 : 3) : (K == 4 ? 2 : 1));
+}
 
 // UNI: every compartment carries the same density mechanisms (flags in mf_uni) and every parameter is uniform
 // (read from the LDS constants, not the per-node table)
 template <int T, int K, typename S, bool UNI>
-__global__ void __launch_bounds__(T, waves_for_shape(T, K)) cn_interval(const KParams p) {
+__global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(const KParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int NMAX = T * K;
   constexpr bool CL = const_in_lds(NMAX);
@@ -1166,6 +1171,18 @@ hipError_t set_interval_lds(bool fp32, int threads, int slots, bool uni, int lds
   if (!fn) return hipErrorInvalidValue;
   return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                              lds_bytes);
+}
+
+// work-groups of the kernel that fit on one CU at once with this much dynamic LDS (registers, LDS and waves)
+hipError_t interval_groups_per_cu(bool fp32, int threads, int slots, bool uni, int lds_bytes, int *n) {
+  IntervalFn fn = interval_fn(fp32, threads, slots, uni);
+  if (!fn) return hipErrorInvalidValue;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, reinterpret_cast<const void *>(fn), threads, lds_bytes);
+}
+
+hipError_t lpc_groups_per_cu(bool fp32, bool uni, int lds_bytes, int *n) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, reinterpret_cast<const void *>(lpc_fn(fp32, uni)), 64,
+                                                      lds_bytes);
 }
 
 hipError_t launch_interval(const KParams &p, bool fp32, int threads, int slots, int lds_bytes, hipStream_t st) {

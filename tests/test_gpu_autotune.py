@@ -71,3 +71,17 @@ def test_every_shape_gives_the_default_results_bitwise(precision):
         assert (info["group_threads"], info["group_slots"]) == (T, K)
         _same(r0, _result(e))
         say(f"  {T}x{K} fill {fill}: {info['n_groups']} groups, identical")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mech"])
+def test_512x2_groups_stay_two_per_cu(precision):
+    """the benchmark's group shape (512 threads x 2 slots, 81 KB of LDS) keeps two groups co-resident on a CU for the
+    uniform kernels (cortex recipe) and the general ones (ring_types: different mechanisms on soma and dendrites);
+    a kernel that outgrows 128 registers would drop this to one and halve the latency hiding of the sweeps"""
+    for m in (synth.cortex_50k(n_cells=300, seed=3), synth.ring_types(n_cells=256, cells_per_type=4)):
+        e = _engine(m, precision=precision, group_threads=512, group_slots=2)
+        e.run_to_step(1)
+        info = e.info()
+        say(f"  {m.name} {precision} 512x2: {info['groups_per_cu']} groups per CU, {info['lds_bytes']} B of LDS")
+        assert (info["group_threads"], info["group_slots"]) == (512, 2)
+        assert info["groups_per_cu"] == 2
