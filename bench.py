@@ -294,8 +294,9 @@ def _brief(r, m, fp32=False):
 
 def other_configs(log, synth):
     """the remaining workloads: clamped_cells (64 x 32, 100 ms), ring_network (1000 x 200, 200 ms FP64; 100 ms in the
-    FP32-mechanism path), cortex_200k (200,000 cells, 50 ms, both precisions). The small ones fit in L2 or the
-    Infinity Cache: their figure is microseconds per time step."""
+    FP32-mechanism path), cortex_200k (200,000 cells, 50 ms, both precisions), and the ring_types workload with and
+    without gap junctions (FP64). The small ones fit in L2 or the Infinity Cache: their figure is microseconds per
+    time step."""
     res = {}
     for name, make, prec, tstop in (("clamped_cells", synth.clamped_cells, "fp64", 100.0),
                                     ("ring_network", synth.ring_network, "fp64", 200.0),
@@ -310,6 +311,19 @@ def other_configs(log, synth):
         res["cortex_200k_" + prec] = _brief(r, m, prec == "fp32_mech")
     res["cortex_200k_fp32_mech"]["speedup_vs_fp64"] = (res["cortex_200k_fp32_mech"]["value"]
                                                        / res["cortex_200k_fp64"]["value"])
+    # gap junctions: the node-ordering workload (131,072 cells x 83 compartments, 8 identical cells per type) with
+    # and without electrical coupling inside clusters of four cells (every pair joined once, 0.01 uS; three joined
+    # sets of 332 compartments fill a 1,024-compartment group as well as the single cells do)
+    for name, gap in (("ring_types_fp64", False), ("ring_types_gap_fp64", True)):
+        m = synth.ring_types(n_cells=131072, cells_per_type=8)
+        if gap:
+            m = synth.add_gap_junctions(m, cluster=4, per_pair=1, g=0.01)
+        log(f"[bench] {name}: {m.n_cells} cells, {m.n_comp} compartments, {m.n_gap} half-gap junctions")
+        r = run_gpu(m, "fp64", 20, 1, log)
+        res[name] = _brief(r, m)
+        res[name]["n_half_gaps"] = int(m.n_gap)
+    res["ring_types_gap_fp64"]["relative_to_uncoupled"] = (res["ring_types_gap_fp64"]["value"]
+                                                           / res["ring_types_fp64"]["value"])
     return res
 
 

@@ -109,3 +109,38 @@ def test_fp32_mech_with_gaps_spikes_within_one_step():
     assert np.array_equal(co, cg)
     oo, og = np.lexsort((so, go)), np.lexsort((sg, gg))
     assert int(np.abs(so[oo] - sg[og]).max()) <= 1
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_junctions_inside_one_cell_and_between_cells(layout):
+    """a half-gap may join two compartments of the same cell (a shunt across its tree) as well as two cells"""
+    m = _ring(n_cells=120, n_comp=60, cluster=2, per_pair=1, g=0.05)
+    rng = np.random.default_rng(77)
+    cells = rng.choice(m.n_cells, 40, replace=False)
+    a = m.cell_offset[cells] + rng.integers(0, 60, 40)
+    b = m.cell_offset[cells] + (a - m.cell_offset[cells] + rng.integers(1, 60, 40)) % 60
+    m.gap_node = np.concatenate([m.gap_node, a, b])
+    m.gap_partner = np.concatenate([m.gap_partner, b, a])
+    m.gap_g = np.concatenate([m.gap_g, np.full(80, 0.02)])
+    say(f"gap junctions inside cells and between them, {m.n_gap} half-gaps, {layout}")
+    orc, eng, worst = lockstep(m, range(100, 2001, 100), layout=layout)
+    assert worst <= 1.0, worst
+    assert_spikes_equal(orc, eng, min_count=10)
+
+
+def test_autotune_on_a_gap_model_keeps_the_results():
+    """the autotuner's candidates that cannot hold a joined pair are skipped; its choice gives the default shape's
+    results bitwise"""
+    from paper_1901_10975_amd import cn
+    m = synth.add_gap_junctions(synth.cortex_50k(n_cells=600, seed=13), cluster=2, per_pair=2, g=0.02)
+    say("autotune on a model with gap junctions")
+    ref = cn.Engine(m)
+    ref.run(5.0)
+    e = cn.Engine(m, autotune=True, tune_budget_ms=60000.0)
+    t = e.tune
+    say(f"  chose {t['layout']} {t['group_threads']}x{t['group_slots']} fill {t['group_fill_pct']} of "
+        f"{len(t['candidates'])} candidates")
+    e.run(5.0)
+    assert np.array_equal(ref.voltages(), e.voltages())
+    for x, y in zip(ref.spikes(), e.spikes()):
+        assert np.array_equal(x, y)
