@@ -1778,8 +1778,9 @@ struct Fnv {
 };
 
 uint64_t tune_signature(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_mechs, const cn_network *net,
-                        const cn_options *opt, double dt) {
+                        const cn_options *opt, double dt, int64_t max_joined) {
   Fnv f;
+  f.put(max_joined);  // compartments of the largest set of cells joined by gap junctions
   f.put(topo->n_cells);
   f.put(topo->n_comp);
   // cell sizes in quarter-octave bins
@@ -1854,7 +1855,16 @@ int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_m
     return fail(CN_E_INVALID, "cell_offset must run from 0 to n_comp");
   cn_options base{};
   if (opt) base = *opt;
-  const uint64_t sig = tune_signature(topo, mechs, n_mechs, net, &base, dt);
+  int32_t max_cell = 0;
+  for (int32_t c = 0; c < topo->n_cells; ++c)
+    max_cell = std::max<int32_t>(max_cell, (int32_t)(topo->cell_offset[c + 1] - topo->cell_offset[c]));
+  {
+    std::vector<int32_t> cl;
+    const int64_t u = join_cells(topo->cell_offset, topo->n_cells, topo->n_comp, net ? net->n_gap : 0,
+                                 net ? net->gap_node : nullptr, net ? net->gap_partner : nullptr, cl);
+    max_cell = (int32_t)std::min<int64_t>(std::max<int64_t>(max_cell, u), INT32_MAX);
+  }
+  const uint64_t sig = tune_signature(topo, mechs, n_mechs, net, &base, dt, max_cell);
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune_cache.find(sig);
@@ -1864,15 +1874,6 @@ int cn_autotune(const cn_topology *topo, const cn_mech_table *mechs, int32_t n_m
       out->n_candidates = 0;
       return CN_OK;
     }
-  }
-  int32_t max_cell = 0;
-  for (int32_t c = 0; c < topo->n_cells; ++c)
-    max_cell = std::max<int32_t>(max_cell, (int32_t)(topo->cell_offset[c + 1] - topo->cell_offset[c]));
-  {
-    std::vector<int32_t> cl;
-    const int64_t u = join_cells(topo->cell_offset, topo->n_cells, topo->n_comp, net ? net->n_gap : 0,
-                                 net ? net->gap_node : nullptr, net ? net->gap_partner : nullptr, cl);
-    max_cell = (int32_t)std::min<int64_t>(std::max<int64_t>(max_cell, u), INT32_MAX);
   }
   int dT = 0, dK = 0;
   default_shape(topo->n_comp, max_cell, dT, dK);
