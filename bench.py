@@ -207,6 +207,9 @@ def main():
                     help="the node-ordering study: ring_types (131,072 cells x 83 compartments, 10 ms) with 1-64 "
                          "identical cells per type on the level and the interleaved layout; prints its own line")
     ap.add_argument("--study-cells", type=int, default=131072)
+    ap.add_argument("--phase-clocks", action="store_true",
+                    help="load the profiling build (libcn_phase.so) and print where the interval kernel's time goes "
+                         "on cortex_50k, per phase, in both precisions; prints its own line")
     args = ap.parse_args()
 
     def log(msg):
@@ -233,6 +236,10 @@ def main():
 
     if args.ordering_study:
         print(json.dumps(ordering_study(log, synth, args.study_cells)), flush=True)
+        return
+
+    if args.phase_clocks:
+        print(json.dumps(phase_clocks(log, synth, args.n_cells, args.steps, args.warmup)), flush=True)
         return
 
     if args.only == "cortex_200k":
@@ -362,6 +369,45 @@ def ordering_study(log, synth, n_cells):
     return {"study": "node ordering (Sec. 4.4)", "workload": f"ring_types: {n_cells} cells x 83 compartments, "
             "hh soma, pas dendrites, one ExpSyn per cell in rings of 128, 10 ms at dt 0.025 ms, FP64",
             "n_comp": n_cells * 83, "rows": rows}
+
+
+def phase_clocks(log, synth, n_cells, steps, warmup):
+    """Per-phase shader clocks of the interval kernel (profiling build) on cortex_50k: the first wave of every group
+    sums the clock between the barriers that close each phase; the sums over the timed intervals, per group-step and
+    as shares. The kernel time from HIP events is printed beside them: the profiling marks cost a few scalar
+    instructions per phase."""
+    import torch
+    from paper_1901_10975_amd import build as B, cn
+
+    if not os.path.exists(B.LIB_PHASE):
+        raise SystemExit(f"{B.LIB_PHASE} is missing: build it with paper_1901_10975_amd/build.py --phase-clocks")
+    cn.LIB_PATH = B.LIB_PHASE
+    m = synth.cortex_50k(n_cells=n_cells)
+    out = {"study": "interval-kernel phases", "workload": f"cortex_50k: {m.n_cells} cells, {m.n_comp} compartments",
+           "library": os.path.basename(B.LIB_PHASE), "phases": list(cn.PHASES)}
+    for prec in ("fp64", "fp32_mech"):
+        eng = cn.Engine(m, precision=prec, timing=True, use_graph=True)
+        eng.run_to_step(1)
+        M = eng.info()["interval_steps"]
+        eng.run_to_step(max(1, warmup) * M)
+        c0, (ms0, l0) = eng.phase_clocks(), eng.stats()
+        n0 = eng.info()["step"]
+        eng.run_to_step(n0 + steps * M)
+        torch.cuda.synchronize()
+        c1, (ms1, l1) = eng.phase_clocks(), eng.stats()
+        info = eng.info()
+        d = {k: c1[k] - c0[k] for k in c1}
+        tot = sum(d.values())
+        gs = info["n_groups"] * steps * M
+        rec = {"kernel_ms": (ms1 - ms0) / max(1, l1 - l0), "group_shape": [info["group_threads"], info["group_slots"]],
+               "groups_per_cu": info["groups_per_cu"], "n_groups": info["n_groups"],
+               "cycles_per_group_step": {k: v / gs for k, v in d.items()},
+               "share": {k: v / tot for k, v in d.items()}}
+        log(f"[phases] {prec}: interval kernel {rec['kernel_ms']:.3f} ms; per group-step cycles "
+            + ", ".join(f"{k} {v:.0f}" for k, v in rec["cycles_per_group_step"].items()))
+        out[prec] = rec
+        eng.close()
+    return out
 
 
 def run_gpu_whole(m, precision, tstop, log):

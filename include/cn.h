@@ -281,6 +281,16 @@ int cn_model_info(const cn_model *m, cn_info *out);
  * from HIP events recorded on the model's stream around each launch. */
 int cn_stats(const cn_model *m, double *kernel_ms, int64_t *kernel_launches);
 
+/* Where a step's time goes (Sec. 2 lists the operations of a step; Sec. 4.4 finds the tree solve's ordering decisive
+ * on GPUs). In a library built with CN_PHASE_CLOCKS (the profiling build, libcn_phase.so) the level layout's interval
+ * kernel sums the shader clock of its first wave per phase over all groups and runs: out[0] a chunk's prologue and
+ * epilogue (rows on chip, event sort, write-back), then per step out[1] events, threshold detection and synapse
+ * staging, out[2] mechanisms and matrix assembly, out[3] the elimination, out[4] the root solves, out[5] the
+ * substitution. out holds n >= CN_N_PHASES entries (host memory, caller-owned). CN_E_STATE from an ordinary build, a
+ * validate-only model or the interleaved layout; CN_E_INVALID on NULL or a short buffer. */
+#define CN_N_PHASES 6
+int cn_phase_clocks(const cn_model *m, uint64_t *out, int32_t n);
+
 /* Free everything the model owns (the counterpart of the memory setup of Sec. 3.1). NULL is a no-op. */
 void cn_model_destroy(cn_model *m);
 

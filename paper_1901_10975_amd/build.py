@@ -20,27 +20,38 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+LIB_PHASE = os.path.join(PKG, "libcn_phase.so")
+
+
+def build(verbose: bool = False, phase_clocks: bool = False) -> str:
+    """Compile the sources (in parallel) and link the library. phase_clocks: the profiling build (libcn_phase.so),
+    whose interval kernel sums its shader clock per phase (cn_phase_clocks)."""
+    lib = LIB_PHASE if phase_clocks else LIB
+    tag = "_phase" if phase_clocks else ""
+    extra = ["-DCN_PHASE_CLOCKS"] if phase_clocks else []
+    objs, procs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", "-I", os.path.join(ROOT, "include"),
-                                                               "-I", CSRC, path, "-o", obj]
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + tag + ".o")
+        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + extra + ["-c", "-I", os.path.join(ROOT, "include"),
+                                                                       "-I", CSRC, path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    for cmd, p in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, phase_clocks="--phase-clocks" in sys.argv))

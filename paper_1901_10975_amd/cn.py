@@ -22,8 +22,9 @@ MECH_ID = {"hh": 0, "pas": 1, "km": 2, "cahi": 3, "expsyn": 4, "iclamp": 5}
 PRECISION = {"fp64": 0, "fp32_mech": 1}
 LAYOUT = {"auto": 0, "level": 1, "interleaved": 2}
 EXPORTS = ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_mech_state_noalloc",
-           "cn_restore", "cn_set_seed", "cn_autotune", "cn_model_info", "cn_stats", "cn_model_destroy",
-           "cn_last_error")
+           "cn_restore", "cn_set_seed", "cn_autotune", "cn_model_info", "cn_stats", "cn_phase_clocks",
+           "cn_model_destroy", "cn_last_error")
+PHASES = ("chunk", "events", "mechanisms", "elimination", "roots", "substitution")
 NOALLOC_STATE_MAX = 4194304
 STATE_KEYS = (("hh", 0, "hh_m"), ("hh", 1, "hh_h"), ("hh", 2, "hh_n"), ("km", 0, "km_n"), ("cahi", 0, "cahi_m"),
               ("cahi", 1, "cahi_cai"), ("expsyn", 0, "syn_g"))
@@ -126,10 +127,11 @@ def lib():
                                   C.POINTER(Options), C.c_double, C.c_double, C.POINTER(TuneResult)]
         L.cn_model_info.argtypes = [C.c_void_p, C.POINTER(Info)]
         L.cn_stats.argtypes = [C.c_void_p, _dp, _i64p]
+        L.cn_phase_clocks.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.c_int32]
         L.cn_model_destroy.argtypes = [C.c_void_p]
         L.cn_model_destroy.restype = None
         for f in ("cn_model_create", "cn_run", "cn_spikes", "cn_voltages", "cn_mech_state", "cn_mech_state_noalloc",
-                  "cn_restore", "cn_set_seed", "cn_autotune", "cn_model_info", "cn_stats"):
+                  "cn_restore", "cn_set_seed", "cn_autotune", "cn_model_info", "cn_stats", "cn_phase_clocks"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -369,3 +371,9 @@ class Engine:
         n = C.c_int64()
         _check(lib().cn_stats(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def phase_clocks(self) -> dict:
+        """shader clocks of the interval kernel per phase (a library built with CN_PHASE_CLOCKS only)"""
+        out = (C.c_uint64 * len(PHASES))()
+        _check(lib().cn_phase_clocks(self._h, out, len(PHASES)))
+        return dict(zip(PHASES, (int(x) for x in out)))

@@ -1148,6 +1148,11 @@ static void build_tables(cn_model *m) {
     p.kick_w = m->upload_s(m->kick_w);
   }
   p.lvl_start = m->upload(m->lvl_start);
+#ifdef CN_PHASE_CLOCKS
+  p.phase_clk = m->upload(std::vector<uint64_t>(PH_COUNT, 0));
+#else
+  p.phase_clk = nullptr;
+#endif
   p.n_groups = (int32_t)m->n_groups;
   // readout tables: caller instance -> device node (density mechanisms with states; a dense table shares one) or
   // device synapse (ExpSyn)
@@ -1608,6 +1613,25 @@ int cn_spikes(const cn_model *m, int64_t *n_out, int32_t *gid, int64_t *step, do
     if (t_interp) t_interp[k] = m->sp_t[idx[k]];
   }
   return CN_OK;
+}
+
+int cn_phase_clocks(const cn_model *m, uint64_t *out, int32_t n) {
+  if (!m || !out) return fail(CN_E_INVALID, "NULL argument");
+  if (n < CN_N_PHASES) return fail(CN_E_INVALID, "out needs CN_N_PHASES entries");
+  static_assert(CN_N_PHASES == PH_COUNT, "phase count");
+#ifndef CN_PHASE_CLOCKS
+  return fail(CN_E_STATE, "this library was built without phase clocks (build with CN_PHASE_CLOCKS)");
+#else
+  if (m->dry) return fail(CN_E_STATE, "model was built with validate_only");
+  if (m->lpc) return fail(CN_E_STATE, "phase clocks cover the level layout's interval kernel only");
+  try {
+    HIPCHK(hipStreamSynchronize(m->stream));
+    HIPCHK(hipMemcpy(out, m->kp.phase_clk, PH_COUNT * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  } catch (const Err &e) {
+    return fail(e.code, e.msg);
+  }
+  return CN_OK;
+#endif
 }
 
 int cn_voltages(const cn_model *m, double *v_out, int64_t n_comp) {

@@ -84,6 +84,11 @@ struct GroupDesc {
 // non-uniform density-mechanism parameters, columns of the per-node parameter table
 enum { P_HH_GNA = 0, P_HH_GK, P_HH_GL, P_HH_EL, P_PAS_G, P_PAS_E, P_KM_G, P_CA_G, N_PRM };
 
+// phases of the interval kernel timed by the profiling build (CN_PHASE_CLOCKS): a chunk's prologue and epilogue,
+// then per step the events, detection and synapse staging; the mechanisms and assembly; the elimination; the root
+// solves; the substitution
+enum { PH_CHUNK = 0, PH_EVENTS, PH_MECH, PH_ELIM, PH_ROOT, PH_SUBST, PH_COUNT };
+
 struct KParams {
   const GroupDesc *groups;
   const int32_t *lvl_start;  // per group n_levels + 1 group-local starts
@@ -146,6 +151,7 @@ struct KParams {
   double dt, q10dt;
   double ca_fm, ca_fr, ca_k;  // cahi: 1-exp(-dt/tau_m), 1-exp(-dt/tau_r), 1e4 tau_r / (2 F depth)
   uint64_t bg_thresh;
+  uint64_t *phase_clk;  // [PH_COUNT] shader-clock sums of the interval kernel (profiling builds only), else NULL
 };
 
 enum { FLAG_EV_OVERFLOW = 0, FLAG_REC_OVERFLOW = 1, FLAG_NONFINITE = 2 };

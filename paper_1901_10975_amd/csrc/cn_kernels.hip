@@ -390,6 +390,22 @@ constexpr int waves_for_shape(int T, int K, bool uni) {
   return K <= 1 ? 4 : (K == 2 ? (T >= 512 && !uni ? 4 : 3) : (K == 4 ? 2 : 1));
 }
 
+// Phase clocks (profiling builds only, compiled with CN_PHASE_CLOCKS): each thread adds the shader clock between
+// consecutive marks to a per-phase sum; the marks sit right after the barriers that close a phase, so the first
+// wave's sums are the group's time per phase. Thread 0 adds them to p.phase_clk at the end.
+#ifdef CN_PHASE_CLOCKS
+#define CN_PHASE_MARK(k)                   \
+  do {                                     \
+    const uint64_t now_ = clock64();       \
+    ph_clk[k] += now_ - ph_t0;             \
+    ph_t0 = now_;                          \
+  } while (0)
+#else
+#define CN_PHASE_MARK(k) \
+  do {                   \
+  } while (0)
+#endif
+
 // UNI: every compartment carries the same density mechanisms (flags in mf_uni) and every parameter is uniform
 // (read from the LDS constants, not the per-node table)
 template <int T, int K, typename S, bool UNI>
@@ -422,6 +438,10 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
 
   const int G = blockIdx.x;
   const int t = threadIdx.x;
+#ifdef CN_PHASE_CLOCKS
+  uint64_t ph_clk[PH_COUNT] = {};
+  uint64_t ph_t0 = clock64();
+#endif
   const GroupDesc gd = p.groups[G];
   const int64_t n_begin = p.ctl[0];
   const int64_t n_target = p.ctl[1];
@@ -582,6 +602,7 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
     }
   };
 
+  CN_PHASE_MARK(PH_CHUNK);
   for (int64_t n = n_begin; n < n_end; ++n) {
     const int s = (int)(n - ival * M);
     if (!EARLY) {
@@ -604,6 +625,7 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
       }
       __syncthreads();
     }
+    CN_PHASE_MARK(PH_EVENTS);
     // ---- C: states, currents, conductances and the compartment's own axial terms. Throughput work: it runs at
     // the lower wave priority, so that a co-resident group's latency-bound sweeps issue ahead of it.
     __builtin_amdgcn_s_setprio(0);
@@ -691,6 +713,7 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
     }
     __syncthreads();
     __builtin_amdgcn_s_setprio(2);
+    CN_PHASE_MARK(PH_MECH);
     // the next step's background bits and delivery (FP32 mechanisms), on the upper half of the threads; the
     // elimination's first barrier waits for them
     if (EARLY && n + 1 < n_end && t >= T / 2) bg_and_deliver(n + 1, t - T / 2, T / 2);
@@ -717,6 +740,7 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
         q = nq;
         cur = nxt;
       }
+      CN_PHASE_MARK(PH_ELIM);
       // ---- R: roots (level 0 holds the group's cells in order): solve and v update
       for (; q < hi; q += T) {
         const TriIn x = q == t ? cur : tri_in(q);
@@ -729,6 +753,7 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
         if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
       }
       __syncthreads();
+      CN_PHASE_MARK(PH_ROOT);
       // ---- B: substitution, root to leaves, v += x, BL levels per barrier. A node of the first level of a pass reads
       // its parent's x: x = u - w x_p. A node j levels deeper folds the steps of its j nearest ancestors into its
       // coefficients, x = cu - cw x_a with a its (j+1)-th ancestor (cu <- cu - cw u_p, cw <- -cw w_p, p <- parent of
@@ -790,6 +815,7 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
           cs = ns;
         }
       }
+      CN_PHASE_MARK(PH_SUBST);
     };
     // the same sweeps without the look-ahead, for groups of 64 or more levels (level starts from LDS)
     auto plain_sweeps = [&]() {
@@ -797,6 +823,7 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
         for (int q = lv[L] + t; q < lv[L + 1]; q += T) tri_node<S>(q, tri_in(q), NMAX * 8, w_l, u_l, P_l, Q_l);
         __syncthreads();
       }
+      CN_PHASE_MARK(PH_ELIM);
       for (int q = t; q < lv[1]; q += T) {
         const TriIn x = tri_in(q);
         double d = x.d, rhs = x.r;
@@ -808,6 +835,7 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
         if (!isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
       }
       __syncthreads();
+      CN_PHASE_MARK(PH_ROOT);
       for (int L = 1; L < D; ++L) {
         for (int q = lv[L] + t; q < lv[L + 1]; q += T) {
           const double x = u_l[q] - w_l[q] * P_l[c_par(q)];
@@ -816,6 +844,7 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
         }
         __syncthreads();
       }
+      CN_PHASE_MARK(PH_SUBST);
     };
     if (D < 64) sweeps();
     else plain_sweeps();
@@ -835,6 +864,11 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
     p.gsp_cnt[G] = misc[1];
     if (n_end == (ival + 1) * (int64_t)M) p.ev_cnt[(int64_t)slot * p.n_groups + G] = 0;
   }
+#ifdef CN_PHASE_CLOCKS
+  CN_PHASE_MARK(PH_CHUNK);
+  if (t == 0)
+    for (int k = 0; k < PH_COUNT; ++k) atomicAdd(reinterpret_cast<unsigned long long *>(p.phase_clk + k), ph_clk[k]);
+#endif
 }
 
 // ------------------------------------------------------------------------------------------------------------------

@@ -186,3 +186,15 @@ def test_gap_clusters_share_a_group(layout):
     m.gap_g = np.full(m.gap_node.shape[0], 0.002)
     e = cn.Engine(m, use_torch=False, validate_only=True, layout=layout)
     assert e.info()["n_comp"] == m.n_comp
+
+
+def test_phase_clocks_need_the_profiling_build():
+    """cn_phase_clocks answers only in the CN_PHASE_CLOCKS build; the ordinary library refuses it, and NULL or a short
+    buffer is an argument error"""
+    L = cn.lib()
+    out = (C.c_uint64 * len(cn.PHASES))()
+    assert L.cn_phase_clocks(None, out, len(cn.PHASES)) == cn.CN_E_INVALID
+    e = cn.Engine(_tiny(), use_torch=False, validate_only=True)
+    assert L.cn_phase_clocks(e._h, out, len(cn.PHASES) - 1) == cn.CN_E_INVALID
+    assert L.cn_phase_clocks(e._h, out, len(cn.PHASES)) == cn.CN_E_STATE
+    assert "without phase clocks" in L.cn_last_error().decode()
