@@ -147,7 +147,7 @@ typedef struct cn_options {
                              fail after it began */
   int32_t group_slots;    /* compartments per thread in a cell group (0: auto); with group_threads it sets the group
                              capacity group_threads * group_slots (shapes compiled: 128 x 2/4/8, 256 x 1/2/4,
-                             512 x 2/4/8), as cn_autotune chooses it */
+                             512 x 2/4/8, 1024 x 2), as cn_autotune chooses it */
   int32_t group_fill_pct; /* cells are packed into a group up to this percentage of its capacity (0: 100) */
   int32_t reserved[3];
 } cn_options;

@@ -385,9 +385,10 @@ constexpr int lds_row_bytes(int nmax) { return const_in_lds(nmax) ? 8 * nmax + 6
 // A group of 512 threads puts two waves on every SIMD, so two co-resident groups need four. The general 512 x 2
 // kernels are held to four (a few registers spill); the uniform ones fit in 128 registers under a bound of three,
 // whose schedule is measured 7-10 % faster than the one compiled for four. cn_model_info reports the groups that
-// are co-resident on a CU, so a kernel that outgrows 128 registers shows up there.
+// are co-resident on a CU, so a kernel that outgrows 128 registers shows up there. A group of 1024 threads puts four
+// waves on every SIMD by itself.
 constexpr int waves_for_shape(int T, int K, bool uni) {
-  return K <= 1 ? 4 : (K == 2 ? (T >= 512 && !uni ? 4 : 3) : (K == 4 ? 2 : 1));
+  return T >= 1024 ? 4 : (K <= 1 ? 4 : (K == 2 ? (T >= 512 && !uni ? 4 : 3) : (K == 4 ? 2 : 1)));
 }
 
 // Phase clocks (profiling builds only, compiled with CN_PHASE_CLOCKS): each thread adds the shader clock between
@@ -1167,6 +1168,8 @@ static IntervalFn interval_fn_s(int threads, int slots) {
       case 8: return cn_interval<512, 8, S, UNI>;
       default: break;
     }
+  } else if (threads == 1024) {
+    if (slots == 2) return cn_interval<1024, 2, S, UNI>;
   } else if (threads == 128) {
     switch (slots) {
       case 2: return cn_interval<128, 2, S, UNI>;

@@ -64,7 +64,7 @@ def test_every_shape_gives_the_default_results_bitwise(precision):
     ref.run(10.0)
     r0 = _result(ref)
     assert r0[1][0].size > 0
-    for T, K, fill in ((128, 8, 100), (256, 4, 100), (512, 2, 90), (512, 4, 100)):
+    for T, K, fill in ((128, 8, 100), (256, 4, 100), (512, 2, 90), (512, 4, 100), (1024, 2, 100)):
         e = _engine(m, precision=precision, group_threads=T, group_slots=K, group_fill_pct=fill)
         e.run(10.0)
         info = e.info()
