@@ -607,7 +607,7 @@ def test_philox_avalanche():
     assert 60 < np.mean(flips) < 68
 
 
-def _partitioned_run(m, parts, tstop, max_passes=80):
+def _partitioned_run(m, parts, tstop, max_passes=80, make=None):
     """Run the cells of each partition in a model of their own, as one GPU of a sharded run would. A spike of a
     cell outside the partition reaches the partition's synapses the way the exchange at interval ends delivers it:
     as an event at step k + D with the NetCon's weight, here a kick. The partitions are rerun with the spikes of the
@@ -635,7 +635,7 @@ def _partitioned_run(m, parts, tstop, max_passes=80):
                     ks.append(k + D[sel]); kn.append(local_syn[m.nc_syn[sel]]); kw.append(m.nc_weight[sel])
             sub = dataclasses.replace(sub, kick_step=np.concatenate(ks).astype(np.int64),
                                       kick_syn=np.concatenate(kn).astype(np.int64), kick_weight=np.concatenate(kw))
-            sim = O.OracleSim(sub)
+            sim = O.OracleSim(sub) if make is None else make(sub)
             sim.run_to_step(n_steps)
             gid, step, t = sim.spikes()
             spikes += [(int(cells[g]), int(k), float(x)) for g, k, x in zip(gid, step, t)]
