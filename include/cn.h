@@ -110,10 +110,11 @@ typedef struct cn_network {
   uint64_t seed;                 /* key of the counter-based background streams */
   const int64_t *poisson_key;    /* [n_syn] stream id of each synapse (>= 0), or NULL: the instance index */
   /* Gap junctions (Sec. 1 and Table 1: the Traub and Dentate models' electrical coupling; Sec. 3.5: handled with the
-   * fixed time step; Sec. 5: the voltages a junction reads, exchanged every step), as half-gap instances: instance k puts the current gap_g[k] (v_node - v_partner) nA at
-   * compartment gap_node[k], the partner's potential taken at the start of the step and the compartment's own
-   * implicit. A junction between two compartments is two instances. Cells joined by junctions must fit together
-   * in one cell group (else CN_E_INVALID). At most 15 instances per compartment. */
+   * fixed time step; Sec. 5: the voltages a junction reads, exchanged every step), as half-gap instances: instance k
+   * puts the current gap_g[k] (v_node - v_partner) nA at compartment gap_node[k], the partner's potential taken at
+   * the start of the step and the compartment's own implicit. A junction between two compartments is two instances.
+   * Cells joined by junctions must fit together in one cell group (else CN_E_INVALID; at most 64 cells in the
+   * interleaved layout). At most 15 instances per compartment. */
   int64_t n_gap;
   const int64_t *gap_node;    /* [n_gap] compartment */
   const int64_t *gap_partner; /* [n_gap] compartment whose potential drives the current (!= gap_node) */
