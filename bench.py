@@ -207,6 +207,8 @@ def main():
                     help="the node-ordering study: ring_types (131,072 cells x 83 compartments, 10 ms) with 1-64 "
                          "identical cells per type on the level and the interleaved layout; prints its own line")
     ap.add_argument("--study-cells", type=int, default=131072)
+    ap.add_argument("--study-rows", default="1,2,4,8,16,32,64",
+                    help="identical cells per type of the ordering study's rows (comma-separated)")
     ap.add_argument("--phase-clocks", action="store_true",
                     help="load the profiling build (libcn_phase.so) and print where the interval kernel's time goes "
                          "on cortex_50k, per phase, in both precisions; prints its own line")
@@ -235,7 +237,8 @@ def main():
         del a, b
 
     if args.ordering_study:
-        print(json.dumps(ordering_study(log, synth, args.study_cells)), flush=True)
+        rows = tuple(int(x) for x in args.study_rows.split(","))
+        print(json.dumps(ordering_study(log, synth, args.study_cells, rows)), flush=True)
         return
 
     if args.phase_clocks:
@@ -334,7 +337,7 @@ def other_configs(log, synth):
     return res
 
 
-def ordering_study(log, synth, n_cells):
+def ordering_study(log, synth, n_cells, per_type=(1, 2, 4, 8, 16, 32, 64)):
     """Sec. 4.4's node-ordering experiment on this engine: ring_types (n_cells x 83 compartments, random branching
     per type, hh soma, pas dendrites) for 1 to 64 identical cells per type, 10 ms of simulated time after a one-
     interval warm-up, FP64, on the level layout (constant-depth order, level-parallel solve on chip) and the
@@ -344,7 +347,7 @@ def ordering_study(log, synth, n_cells):
     from paper_1901_10975_amd import cn
 
     rows = []
-    for k in (1, 2, 4, 8, 16, 32, 64):
+    for k in per_type:
         m = synth.ring_types(n_cells=n_cells, cells_per_type=k)
         row = {"cells_per_type": k}
         for layout in ("level", "interleaved"):
