@@ -541,6 +541,10 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
   }
   // level starts, lane L of every wave holding lv[L]: read back with a lane read instead of an LDS round trip
   const int lvr = (t & 63) <= D ? lv[t & 63] : 0;
+  // the deepest level holds leaves only: their elimination needs nothing from other nodes, so the assembly's
+  // write-back does it and the sweeps start one level up (E levels left to them: all of them when D == 1)
+  const int deep0 = D >= 2 ? lv[D - 1] : N;
+  const int E = D >= 2 ? D - 1 : D;
   // synapse terms are staged on chip when the group's synapses fit the rows
   const bool staged = n_syn <= 2 * NMAX;
   __syncthreads();
@@ -707,9 +711,19 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
     for (int j = 0; j < K; ++j) {
       const int q = j * T + t;
       if (q < N) {
-        w_l[q] = od[j];
-        u_l[q] = orhs[j];
-        Q_l[q] = odv[j];
+        if (q < deep0) {
+          w_l[q] = od[j];
+          u_l[q] = orhs[j];
+          Q_l[q] = odv[j];
+        } else {  // a leaf of the deepest level: the elimination of tri_node with no child to gather
+          const double a = c_a(q), adv = a * odv[j];
+          const double ri = rcp64<S>(od[j]);
+          const double w = ri * c_b(q), u = ri * orhs[j];
+          w_l[q] = w;
+          u_l[q] = u;
+          P_l[q] = fma(a, w, a);
+          Q_l[q] = fma(a, u, -adv);
+        }
       }
     }
     __syncthreads();
@@ -721,14 +735,15 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
     // the sweeps; level starts are read from lane registers when the group has fewer than 64 levels
     auto sweeps = [&]() {
       auto LVB = [&](int L) -> int { return __builtin_amdgcn_readlane(lvr, L); };
-      // ---- T: elimination, deepest level first, one thread per node of the level. A level's own inputs are final
+      // ---- T: elimination from the level above the deepest (done in the assembly's write-back) up, one thread per
+      // node of the level. A level's own inputs are final
       // before it starts, so each thread loads them one level ahead; after a barrier only the children's
       // contributions remain to be read.
-      int hi = LVB(D), lo = LVB(D - 1), lo_n = D >= 2 ? LVB(D - 2) : 0;
+      int hi = LVB(E), lo = LVB(E - 1), lo_n = E >= 2 ? LVB(E - 2) : 0;
       int q = lo + t;
       TriIn cur{};
       if (q < hi) cur = tri_in(q);
-      for (int L = D - 1; L >= 1; --L) {  // level L is [lo, hi), level L - 1 is [lo_n, lo)
+      for (int L = E - 1; L >= 1; --L) {  // level L is [lo, hi), level L - 1 is [lo_n, lo)
         const int lo_nn = L >= 2 ? LVB(L - 2) : 0;
         const int nq = lo_n + t;
         const TriIn nxt = tri_in(min(nq, N - 1));  // lanes past the level read the group's last node and ignore it
@@ -820,7 +835,7 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
     };
     // the same sweeps without the look-ahead, for groups of 64 or more levels (level starts from LDS)
     auto plain_sweeps = [&]() {
-      for (int L = D - 1; L >= 1; --L) {
+      for (int L = E - 1; L >= 1; --L) {
         for (int q = lv[L] + t; q < lv[L + 1]; q += T) tri_node<S>(q, tri_in(q), NMAX * 8, w_l, u_l, P_l, Q_l);
         __syncthreads();
       }
