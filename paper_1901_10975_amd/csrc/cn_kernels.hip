@@ -736,9 +736,8 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
     auto sweeps = [&]() {
       auto LVB = [&](int L) -> int { return __builtin_amdgcn_readlane(lvr, L); };
       // ---- T: elimination from the level above the deepest (done in the assembly's write-back) up, one thread per
-      // node of the level. A level's own inputs are final
-      // before it starts, so each thread loads them one level ahead; after a barrier only the children's
-      // contributions remain to be read.
+      // node of the level. A level's own inputs are final before it starts, so each thread loads them one level
+      // ahead; after a barrier only the children's contributions remain to be read.
       int hi = LVB(E), lo = LVB(E - 1), lo_n = E >= 2 ? LVB(E - 2) : 0;
       int q = lo + t;
       TriIn cur{};
