@@ -384,6 +384,8 @@ def phase_clocks(log, synth, n_cells, steps, warmup):
 
     if not os.path.exists(B.LIB_PHASE):
         raise SystemExit(f"{B.LIB_PHASE} is missing: build it with paper_1901_10975_amd/build.py --phase-clocks")
+    if cn._lib is not None and cn.LIB_PATH != B.LIB_PHASE:
+        raise SystemExit("the ordinary library is already loaded in this process; run --phase-clocks on its own")
     cn.LIB_PATH = B.LIB_PHASE
     m = synth.cortex_50k(n_cells=n_cells)
     out = {"study": "interval-kernel phases", "workload": f"cortex_50k: {m.n_cells} cells, {m.n_comp} compartments",
