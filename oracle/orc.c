@@ -24,7 +24,7 @@
  *   R3 gate update: x += (1 - exp(-dt/tau)) (xinf - x) with v frozen over the step.
  *   R4 hh: the Hodgkin-Huxley 1952 squid-axon rates in the modern sign convention (rest near -65 mV), ena = 50 mV,
  *      ek = -77 mV, q10 = 3^((celsius - 6.3)/10); vtrap(x, y) = x/(exp(x/y)-1), or y(1 - x/y/2) when |x/y| < 1e-6.
- *   R5 km and cahi are project-defined (parity unpinned beyond closed-form and balance checks):
+ *   R5 km and cahi are project-defined (pinned by held-voltage relaxation and steady-state tests):
  *      km:   ninf = 1/(1+exp(-(v+35)/10)), tau = 400/(3.3 exp((v+35)/20) + exp(-(v+35)/20)) ms, i = gbar n (v-ek);
  *      cahi: minf = 1/(1+exp(-(v+20)/9)), tau_m = 1 ms, i = gbar m^2 (v-eca), eca = 120 mV; calcium in a 0.1 um
  *            shell: dcai/dt = -1e4 ica/(2 F depth) - (cai - cai0)/tau_r, cai0 = 5e-5 mM, tau_r = 80 ms, integrated
@@ -40,6 +40,10 @@
  *      seed high) and counter (k low, k high, n/4 low, n/4 high). Its weight is that synapse's background weight.
  *   R10 IClamp: on for steps n with ceil(del/dt - 0.5) <= n < ceil((del+dur)/dt - 0.5).
  *   R11 ExpSyn: g decays as g exp(-dt/tau) after the solve; i = g (v - e) nA.
+ *   R13 gap junctions: half-gap instances, each a current g (v_i - v_partner) nA at compartment i with the partner's
+ *      potential from the start of the step and the own potential implicit (g on the diagonal).
+ * Philox4x32-10 (R9) is parity unpinned: its statistics are tested, its identity with the published streams is not
+ * (no known-answer vectors here).
  */
 #include "orc.h"
 
