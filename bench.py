@@ -52,9 +52,9 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def _profile(path, precision):
+def _profile(path, precision, info=None):
     """one kernel's record of a committed counter profile, or None when the kernel sources changed since it was
-    taken"""
+    taken, or when the run (its cn_model_info) used another group shape than the profiled kernel"""
     try:
         with open(path) as fh:
             rec = json.load(fh)
@@ -62,7 +62,12 @@ def _profile(path, precision):
         return None
     if rec.get("source_sha256") != kernel_sources_sha256():
         return None
-    return rec.get("kernels", {}).get(precision)
+    k = rec.get("kernels", {}).get(precision)
+    if k is not None and info is not None:
+        shape = f"cn_interval<{info['group_threads']}, {info['group_slots']},"
+        if info.get("layout") != 1 or shape not in k.get("kernel", ""):
+            return None
+    return k
 
 
 def run_gpu(m, precision, steps, warmup, log, **kw):
@@ -71,7 +76,14 @@ def run_gpu(m, precision, steps, warmup, log, **kw):
 
     t0 = time.time()
     eng = cn.Engine(m, precision=precision, timing=True, use_graph=True, **kw)
-    log(f"[bench] {m.name} {precision}: model built in {time.time() - t0:.1f} s")
+    tune = eng.tune
+    if tune is not None:
+        log(f"[bench] {m.name} {precision}: autotuned in {time.time() - t0:.1f} s: {tune['layout']} "
+            f"{tune['group_threads']}x{tune['group_slots']} fill {tune['group_fill_pct']} at {tune['interval_ms']:.3f} ms "
+            f"per interval (default {tune['default_threads']}x{tune['default_slots']} {tune['default_ms']:.3f} ms, "
+            f"{len(tune['candidates'])} candidates)")
+    log(f"[bench] {m.name} {precision}: model {'tuned and ' if tune is not None else ''}built in "
+        f"{time.time() - t0:.1f} s")
     eng.run_to_step(1)  # fixes dt, hence the interval length, and captures the interval graph
     M = eng.info()["interval_steps"]
     eng.run_to_step(max(1, warmup) * M)
@@ -88,7 +100,7 @@ def run_gpu(m, precision, steps, warmup, log, **kw):
     kernel_ms = (ms1 - ms0) / max(1, launches)
     g, s, _ = eng.spikes()
     res = dict(wall=wall, M=M, steps=steps, kernel_ms=kernel_ms, launches=launches, info=info,
-               n_spikes=int(g.size), comp_steps=float(m.n_comp) * steps * M)
+               n_spikes=int(g.size), comp_steps=float(m.n_comp) * steps * M, tune=tune)
     res["value"] = res["comp_steps"] / wall
     res["us_per_step"] = wall / (steps * M) * 1e6
     log(f"[bench] {m.name} {precision}: {steps} intervals x {M} steps in {wall:.3f} s -> {res['value']:.4e} "
@@ -163,9 +175,9 @@ def roofline(m, r64, fp32_res=None):
     per_launch = bytes_per_step(m, False) * r64["M"]
     kern_s = r64["kernel_ms"] * 1e-3
     eff_gbs = per_launch / kern_s / 1e9
-    tr = _profile(PROFILE, "fp64")
+    tr = _profile(PROFILE, "fp64", r64["info"])
     traffic = None if tr is None else float(tr["traffic_bytes"])
-    cnt = _profile(VALU_PROFILE, "fp64")
+    cnt = _profile(VALU_PROFILE, "fp64", r64["info"])
     alu = None
     if cnt is not None:
         lane = float(cnt["valu_lane_insts_per_comp_step"]) * m.n_comp * r64["M"] / kern_s
@@ -197,6 +209,8 @@ def main():
     ap.add_argument("--n-cells", type=int, default=50000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the main workload at the default cell-group shape instead of the autotuner's choice")
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip clamped_cells, ring_network and cortex_200k")
     ap.add_argument("--only", choices=["cortex_50k", "cortex_200k"], default=None,
@@ -258,8 +272,9 @@ def main():
     m = synth.cortex_50k(n_cells=args.n_cells)
     log(f"[bench] cortex_50k: {m.n_cells} cells, {m.n_comp} compartments, {m.n_syn} synapses "
         f"(generated in {time.time() - t0:.1f} s)")
-    r64 = run_gpu(m, "fp64", args.steps, args.warmup, log)
-    r32 = None if args.no_fp32 else run_gpu(m, "fp32_mech", args.steps, args.warmup, log)
+    tkw = {} if args.no_autotune else {"autotune": True, "tune_budget_ms": 60000.0}
+    r64 = run_gpu(m, "fp64", args.steps, args.warmup, log, **tkw)
+    r32 = None if args.no_fp32 else run_gpu(m, "fp32_mech", args.steps, args.warmup, log, **tkw)
 
     out = {
         "metric": "compartment-timesteps/sec at 50k cells (FP64 vs FP32-mech); HBM GB/s fraction",
@@ -278,12 +293,16 @@ def main():
                                "100 ExpSyn/cell, NetCon delay U(1,5) ms, Poisson 5 Hz, dt 0.025 ms; one step = one "
                                "1 ms min-delay interval (40 time steps)" % m.n_comp,
                    "n_cells": m.n_cells, "n_comp": m.n_comp, "n_syn": m.n_syn, "interval_steps": r64["M"],
-                   "group_threads": r64["info"]["group_threads"], "group_slots": r64["info"]["group_slots"]},
+                   "group_threads": r64["info"]["group_threads"], "group_slots": r64["info"]["group_slots"],
+                   "layout": "interleaved" if r64["info"]["layout"] == 2 else "level",
+                   "autotune": _tune_brief(r64["tune"])},
         "us_per_time_step": r64["us_per_step"],
         "roofline": roofline(m, r64),
     }
     if r32 is not None:
         out["fp32_mech"] = _brief(r32, m, True)
+        out["fp32_mech"]["group_shape"] = [r32["info"]["group_threads"], r32["info"]["group_slots"]]
+        out["fp32_mech"]["autotune"] = _tune_brief(r32["tune"])
         out["fp32_mech"]["speedup_vs_fp64"] = r32["value"] / r64["value"]
         out["fp32_mech"]["meets_1p5x_target"] = bool(r32["value"] / r64["value"] >= 1.5)
     if not args.no_other_configs and args.only is None:
@@ -294,12 +313,23 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def _tune_brief(t):
+    """the autotuner's choice for a bench line (None when the default shape ran)"""
+    if t is None:
+        return None
+    return {"chosen": f"{t['layout']} {t['group_threads']}x{t['group_slots']} fill {t['group_fill_pct']}",
+            "interval_ms": t["interval_ms"], "default": f"level {t['default_threads']}x{t['default_slots']} fill 100",
+            "default_ms": t["default_ms"], "gain_over_default": t["default_ms"] / t["interval_ms"],
+            "candidates": [f"{c['layout']} {c['threads']}x{c['slots']} fill {c['fill_pct']}: {c['interval_ms']:.3f} ms"
+                           for c in t["candidates"]]}
+
+
 def _brief(r, m, fp32=False):
     bps = bytes_per_step(m, fp32)
     return {"value": r["value"], "unit": "compartment-timesteps/s", "us_per_time_step": r["us_per_step"],
             "interval_steps": r["M"], "kernel_ms": r["kernel_ms"],
             "effective_hbm_frac": bps * r["M"] / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "counters": _profile(VALU_PROFILE, "fp32_mech" if fp32 else "fp64")}
+            "counters": _profile(VALU_PROFILE, "fp32_mech" if fp32 else "fp64", r["info"])}
 
 
 def other_configs(log, synth):
