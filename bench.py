@@ -223,6 +223,10 @@ def main():
     ap.add_argument("--study-cells", type=int, default=131072)
     ap.add_argument("--study-rows", default="1,2,4,8,16,32,64",
                     help="identical cells per type of the ordering study's rows (comma-separated)")
+    ap.add_argument("--restart-study", action="store_true",
+                    help="checkpoint-restart at full size (cortex_50k, both precisions): time the checkpoint and the "
+                         "restore, and check that the split run equals the uninterrupted one bitwise; prints its own "
+                         "line")
     ap.add_argument("--phase-clocks", action="store_true",
                     help="load the profiling build (libcn_phase.so) and print where the interval kernel's time goes "
                          "on cortex_50k, per phase, in both precisions; prints its own line")
@@ -253,6 +257,10 @@ def main():
     if args.ordering_study:
         rows = tuple(int(x) for x in args.study_rows.split(","))
         print(json.dumps(ordering_study(log, synth, args.study_cells, rows)), flush=True)
+        return
+
+    if args.restart_study:
+        print(json.dumps(restart_study(log, synth, args.n_cells)), flush=True)
         return
 
     if args.phase_clocks:
@@ -402,6 +410,58 @@ def ordering_study(log, synth, n_cells, per_type=(1, 2, 4, 8, 16, 32, 64)):
     return {"study": "node ordering (Sec. 4.4)", "workload": f"ring_types: {n_cells} cells x 83 compartments, "
             "hh soma, pas dendrites, one ExpSyn per cell in rings of 128, 10 ms at dt 0.025 ms, FP64",
             "n_comp": n_cells * 83, "rows": rows}
+
+
+def restart_study(log, synth, n_cells, n_split=6, n_end=12):
+    """Checkpoint-restart (Sec. 3.4) on the benchmark workload: run to interval n_split, take the checkpoint (the
+    readouts: potentials, every state, the spikes), restore it into a fresh model and continue to interval n_end;
+    the continued run must equal the uninterrupted one bitwise (potentials, states, the spikes after the split)."""
+    import numpy as np
+    import torch
+    from paper_1901_10975_amd import cn
+
+    m = synth.cortex_50k(n_cells=n_cells)
+    out = {"study": "checkpoint-restart", "workload": f"cortex_50k: {m.n_cells} cells, {m.n_comp} compartments"}
+    for prec in ("fp64", "fp32_mech"):
+        whole = cn.Engine(m, precision=prec)
+        whole.run_to_step(1)
+        M = whole.info()["interval_steps"]
+        whole.run_to_step(n_end * M)
+        a = cn.Engine(m, precision=prec)
+        a.run_to_step(n_split * M + M // 2)  # inside an interval: events in flight, a pending state update
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ck = a.checkpoint()
+        t_ck = time.perf_counter() - t0
+        nbytes = sum(np.asarray(x).nbytes for x in (ck["v"], ck["gid"], ck["spike_step"])) + \
+            sum(x.nbytes for x in ck["states"].values())
+        a.close()
+        t0 = time.perf_counter()
+        b = cn.Engine(m, precision=prec)
+        t_build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        b.restore(ck)
+        torch.cuda.synchronize()
+        t_restore = time.perf_counter() - t0
+        b.run_to_step(n_end * M)
+        cw, cb = whole.checkpoint(), b.checkpoint()
+        same = bool(np.array_equal(cw["v"], cb["v"]) and all(np.array_equal(cw["states"][k], cb["states"][k])
+                                                            for k in cw["states"]))
+        gw, sw, tw = whole.spikes()
+        gb, sb, tb = b.spikes()
+        keep = sw > ck["step"]
+        same_spikes = bool(np.array_equal(gw[keep], gb) and np.array_equal(sw[keep], sb) and
+                           np.array_equal(tw[keep], tb))
+        rec = {"split_step": int(ck["step"]), "end_step": n_end * M, "checkpoint_s": t_ck, "checkpoint_bytes": nbytes,
+               "model_build_s": t_build, "restore_s": t_restore, "spikes_before_split": int(ck["gid"].size),
+               "spikes_after_split": int(gb.size), "identical_state": same, "identical_spikes": same_spikes}
+        log(f"[restart] {prec}: checkpoint at step {ck['step']} in {t_ck:.2f} s ({nbytes / 1e6:.0f} MB), restore "
+            f"{t_restore:.2f} s after a {t_build:.1f} s build; {gb.size} spikes after the split; identical "
+            f"{same and same_spikes}")
+        out[prec] = rec
+        for e in (whole, b):
+            e.close()
+    return out
 
 
 def phase_clocks(log, synth, n_cells, steps, warmup):
