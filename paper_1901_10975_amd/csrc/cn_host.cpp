@@ -944,11 +944,11 @@ static void build_tables(cn_model *m) {
       p.prm_s[c] = tb.present ? tb.p[cols[c][1]].s : 0.0;
       if (tb.present && !tb.p[cols[c][1]].uniform) any = true;
     }
-    // the uniform kernels also need one mechanism set on every compartment and carry no gap-junction terms;
-    // otherwise the parameters go to the table as well
+    // the uniform kernels also need one mechanism set on every compartment and carry no gap-junction terms; the
+    // general kernels read uniform parameters from the same constants and take the table only when a column varies
     const bool same_mechs = N == 0 || std::all_of(mf.begin(), mf.end(), [&](uint8_t x) { return x == mf[0]; });
     p.mf_uni = N ? mf[0] : 0;
-    if (!same_mechs || m->n_gap > 0) any = true;
+    p.uni = !any && same_mechs && m->n_gap == 0;
     p.prm = nullptr;
     if (any) {
       std::vector<double> t(N_PRM * (size_t)N, 0.0);
@@ -1340,11 +1340,11 @@ static void prepare_dt(cn_model *m, double dt) {
     throw Err{CN_E_INVALID, "cell groups need " + std::to_string(m->lds_bytes) + " bytes of LDS (event_capacity "
                                 "or synapses per group too large)"};
   if (m->lpc) {
-    HIPCHK(set_lpc_lds(m->fp32, p.prm == nullptr, m->lds_bytes));
-    HIPCHK(lpc_groups_per_cu(m->fp32, p.prm == nullptr, m->lds_bytes, &m->groups_per_cu));
+    HIPCHK(set_lpc_lds(m->fp32, p.uni != 0, m->lds_bytes));
+    HIPCHK(lpc_groups_per_cu(m->fp32, p.uni != 0, m->lds_bytes, &m->groups_per_cu));
   } else {
-    HIPCHK(set_interval_lds(m->fp32, m->threads, m->slots, p.prm == nullptr, m->lds_bytes));
-    HIPCHK(interval_groups_per_cu(m->fp32, m->threads, m->slots, p.prm == nullptr, m->lds_bytes, &m->groups_per_cu));
+    HIPCHK(set_interval_lds(m->fp32, m->threads, m->slots, p.uni != 0, m->lds_bytes));
+    HIPCHK(interval_groups_per_cu(m->fp32, m->threads, m->slots, p.uni != 0, m->lds_bytes, &m->groups_per_cu));
   }
   HIPCHK(hipStreamSynchronize(m->stream));
   if (m->opt.use_graph) {

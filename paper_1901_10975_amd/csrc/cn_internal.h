@@ -100,6 +100,7 @@ struct KParams {
   int32_t has_bg;
   uint32_t mf_uni;   // the density-mechanism flags every compartment carries (kernels for uniform models)
   int32_t has_icl;   // any IClamp in the model
+  int32_t uni;       // the uniform kernels run: one mechanism set everywhere, every parameter uniform, no gap junction
   int32_t lds_ev_off, lds_seg_off, lds_lvl_off, lds_bg_off, lds_cell_off, lds_misc_off, lds_cst_off, lds_exp_off;
   const double *exp_tab;   // 2^(j/64), j = 0..63
   // node tables (device order)

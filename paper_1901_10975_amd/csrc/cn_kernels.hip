@@ -493,7 +493,8 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
   // arguments, FP64 kernels from the LDS copy
   constexpr bool KARG = std::is_same<S, float>::value;
   auto prm = [&](int col, int64_t i) -> double {
-    return UNI ? (KARG ? p.prm_s[col] : cst[C_PRM + col]) : p.prm[col * p.n_nodes_total + i];
+    if (UNI) return KARG ? p.prm_s[col] : cst[C_PRM + col];
+    return p.prm ? p.prm[col * p.n_nodes_total + i] : cst[C_PRM + col];  // a column that varies: the table
   };
   StRec<S> *st = static_cast<StRec<S> *>(p.st);
   const SynRec<S> *syn = static_cast<const SynRec<S> *>(p.syn) + sb;
@@ -931,7 +932,9 @@ __global__ void __launch_bounds__(64) cn_lpc(const KParams p) {
   const SynRec<S> *syn = static_cast<const SynRec<S> *>(p.syn) + gd.syn_base;
   S *sg = static_cast<S *>(p.syn_g) + gd.syn_base;
   double *V = p.v, *Dw = p.lw_d, *Rw = p.lw_r, *DVw = p.lw_dv;
-  auto prm = [&](int col, int64_t i) -> double { return UNI ? p.prm_s[col] : p.prm[col * p.n_nodes_total + i]; };
+  auto prm = [&](int col, int64_t i) -> double {
+    return (UNI || !p.prm) ? p.prm_s[col] : p.prm[col * p.n_nodes_total + i];
+  };
   const S q10dt = (S)p.q10dt, sdt = (S)p.dt, ca_fm = (S)p.ca_fm, ca_fr = (S)p.ca_fr, ca_k = (S)p.ca_k;
   double vold = act ? V[nb] : 0.0;
   int nspk = 0;  // spikes of the chunk so far (uniform across the wave)
@@ -1211,7 +1214,7 @@ hipError_t set_lpc_lds(bool fp32, bool uni, int lds_bytes) {
 }
 
 hipError_t launch_lpc(const KParams &p, bool fp32, int lds_bytes, hipStream_t st) {
-  hipLaunchKernelGGL(lpc_fn(fp32, p.prm == nullptr), dim3(p.n_groups), dim3(64), lds_bytes, st, p);
+  hipLaunchKernelGGL(lpc_fn(fp32, p.uni != 0), dim3(p.n_groups), dim3(64), lds_bytes, st, p);
   return hipGetLastError();
 }
 
@@ -1237,7 +1240,7 @@ hipError_t lpc_groups_per_cu(bool fp32, bool uni, int lds_bytes, int *n) {
 }
 
 hipError_t launch_interval(const KParams &p, bool fp32, int threads, int slots, int lds_bytes, hipStream_t st) {
-  IntervalFn fn = interval_fn(fp32, threads, slots, p.prm == nullptr);
+  IntervalFn fn = interval_fn(fp32, threads, slots, p.uni != 0);
   if (!fn) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(p.n_groups), dim3(threads), lds_bytes, st, p);
   return hipGetLastError();
