@@ -94,12 +94,13 @@ def test_split_run_with_gaps(layout):
     assert np.array_equal(gw[keep], gb) and np.array_equal(sw[keep], sb)
 
 
-def test_fp32_mech_with_gaps_spikes_within_one_step():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_fp32_mech_with_gaps_spikes_within_one_step(layout):
     from paper_1901_10975_amd import cn
     m = synth.add_gap_junctions(synth.cortex_50k(n_cells=400, seed=29), cluster=2, per_pair=2, g=0.02)
-    say("gap junctions, fp32_mech against the FP64 oracle")
+    say(f"gap junctions, fp32_mech against the FP64 oracle, {layout}")
     orc = O.OracleSim(m, n_threads=16)
-    eng = cn.Engine(m, precision="fp32_mech")
+    eng = cn.Engine(m, precision="fp32_mech", layout=layout)
     orc.run(20.0)
     eng.run(20.0)
     go, so, _ = orc.spikes()

@@ -105,3 +105,21 @@ def test_fp32_mech_interleaved_spikes_within_one_step():
     assert np.array_equal(co, cg)
     oo, og = np.lexsort((so, go)), np.lexsort((sg, gg))
     assert int(np.abs(so[oo] - sg[og]).max()) <= 1
+
+
+def test_per_compartment_parameters_interleaved():
+    """per-compartment parameters (the table path of the general kernels) in the interleaved layout"""
+    m = synth.ring_network(n_cells=120, n_comp=150, seed=31)
+    rng = np.random.default_rng(31)
+    hh = m.mechs["hh"]
+    k = m.n_comp if hh.node is None else hh.node.size
+    hh.params["gnabar"] = rng.uniform(0.08, 0.16, k)
+    hh.params["gkbar"] = rng.uniform(0.02, 0.05, k)
+    hh.params["gl"] = rng.uniform(1e-4, 5e-4, k)
+    hh.params["el"] = rng.uniform(-60.0, -50.0, k)
+    m.nc_weight = m.nc_weight * 4
+    say("interleaved: per-compartment parameters")
+    orc, eng, worst = lockstep(m, range(100, 1001, 100), **IL)
+    assert worst <= 1.0, worst
+    assert_spikes_equal(orc, eng, min_count=20)
+
