@@ -922,8 +922,9 @@ static void build_tables(cn_model *m) {
   m->host_ch = ch;
   p.v = m->upload(std::vector<double>(N, m->v_init));
   if (m->lpc) {
-    p.lw_d = static_cast<double *>(m->dalloc(N * sizeof(double)));
-    p.lw_r = static_cast<double *>(m->dalloc(N * sizeof(double)));
+    // the elimination's accumulators start at zero (each step's substitution returns them there)
+    p.lw_d = m->upload(std::vector<double>(N, 0.0));
+    p.lw_r = m->upload(std::vector<double>(N, 0.0));
     p.lw_dv = static_cast<double *>(m->dalloc(N * sizeof(double)));
   }
   {

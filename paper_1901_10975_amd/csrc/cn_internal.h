@@ -146,7 +146,8 @@ struct KParams {
   int32_t *flags;          // [0] event overflow, [1] spike record overflow, [2] non-finite voltage
   int64_t *ctl;            // [0] first step of the next chunk, [1] target step, [2] the step whose channel states
                            // carry no pending update (0, or the step of a restart), [3] key of the background streams
-  // interleaved layout (one lane per cell): per-node work arrays of the tree solve
+  // interleaved layout (one lane per cell): per-node work arrays of the tree solve: the elimination's accumulators of
+  // the diagonal and right-hand side (zero between steps; w and u once a compartment is eliminated), the solution x
   double *lw_d, *lw_r, *lw_dv;
   // constants
   double dt, q10dt;

@@ -892,12 +892,12 @@ __global__ void __launch_bounds__(T, waves_for_shape(T, K, UNI)) cn_interval(con
 // cells, one per lane of a single wave, whose compartments are interleaved in global memory: compartment k of lane j
 // sits at node_base + 64 k + j, in the caller's order (root first, parent before child), the group padded to its
 // largest cell with inert compartments (d = 1, no terms, parent the root). Each lane advances its own cell through
-// the chunk with no barrier: delivery and background events of its synapses, states, currents and assembly in one
-// pass over its compartments, then the serial elimination from the last compartment to the root and the
-// substitution back (Sec. 2, Gaussian elimination in the Hines order). Accesses are coalesced across the wave when
-// the 64 cells share the parent index of a compartment (identical cells), strided otherwise: the effect the paper
-// measures. The tree work arrays (d, rhs, dv) live in global memory. Threshold detection at the root, compacted in
-// cell order with a wave ballot.
+// the chunk with no barrier: delivery and background events of its synapses, then one pass over its compartments
+// from the last to the root doing each one's states, currents, assembly and elimination (Sec. 2, Gaussian
+// elimination in the Hines order), then the substitution back. Accesses are coalesced across the wave when the 64
+// cells share the parent index of a compartment (identical cells), strided otherwise: the effect the paper measures.
+// The tree work arrays (the elimination's accumulators, later w and u; the solution x) live in global memory.
+// Threshold detection at the root, compacted in cell order with a wave ballot.
 template <typename S, bool UNI>
 __global__ void __launch_bounds__(64) cn_lpc(const KParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -951,9 +951,13 @@ __global__ void __launch_bounds__(64) cn_lpc(const KParams p) {
     }
     // background-event bits of the cell's synapses are drawn for a block of four steps
     const bool draw = p.has_bg && (n == n_begin || (n & 3) == 0);
-    // states, currents and conductances, synapses, and the compartment's own matrix terms
+    // One pass over the compartments, last first: each compartment's states, currents and conductances, synapses
+    // and own matrix terms, then its elimination, since its children (higher indices) are done. A child passes
+    // a (w + 1) and a (u - dv) to its parent through the accumulators Dw, Rw (the parent's axial terms folded in),
+    // which the substitution leaves at zero for the next step; the compartment's w, u take their place.
     const bool pend = n > n_fresh;
-    for (int k = 0; k < KN; ++k) {
+    double vnew = 0.0;
+    for (int k = KN - 1; k >= 0; --k) {
       const int64_t i = nb + 64 * (int64_t)k;
       const NodeIdx nx = p.nidx[i];
       const NodeRec nr = p.nrec[i];
@@ -999,38 +1003,34 @@ __global__ void __launch_bounds__(64) cn_lpc(const KParams p) {
         dv = V[nb + 64 * (int64_t)nx.par] - v;
         rhs -= nr.b * dv;
       }
-      Dw[i] = d;
-      Rw[i] = rhs;
-      DVw[i] = dv;
+      d += Dw[i];  // the children's contributions (zero for a leaf)
+      rhs += Rw[i];
+      if (k > 0) {
+        const int64_t ip = nb + 64 * (int64_t)nx.par;
+        const double ri = rcp64<S>(d);
+        const double w = ri * nr.b, u = ri * rhs;
+        Dw[i] = w;
+        Rw[i] = u;
+        Dw[ip] -= fma(nr.a, w, nr.a);
+        Rw[ip] -= fma(nr.a, u, -(nr.a * dv));
+      } else {  // the root (compartment 0 of the lane's cell): solve, v update, threshold detection below
+        const double xs = rhs * rcp64<S>(d);
+        vnew = dv + xs;
+        DVw[nb] = xs;
+        V[nb] = vnew;
+        Dw[nb] = 0.0;
+        Rw[nb] = 0.0;
+        if (act && !isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
+      }
     }
-    // elimination, last compartment first: each compartment, final once its children (higher indices) are done,
-    // passes a (w + 1) and a (u - dv) to its parent's row (the parent's axial terms folded in)
-    for (int k = KN - 1; k >= 1; --k) {
-      const int64_t i = nb + 64 * (int64_t)k;
-      const double d = Dw[i], r = Rw[i], dv = DVw[i];
-      const NodeRec nr = p.nrec[i];
-      const int64_t ip = nb + 64 * (int64_t)p.nidx[i].par;
-      const double ri = rcp64<S>(d);
-      const double w = ri * nr.b, u = ri * r;
-      Dw[i] = w;
-      Rw[i] = u;
-      Dw[ip] -= fma(nr.a, w, nr.a);
-      Rw[ip] -= fma(nr.a, u, -(nr.a * dv));
-    }
-    // the root, threshold detection at it, and the substitution: x = u - w x_parent, v += x
-    double vnew = 0.0;
-    {
-      const double xs = Rw[nb] * rcp64<S>(Dw[nb]);
-      vnew = DVw[nb] + xs;
-      Rw[nb] = xs;
-      V[nb] = vnew;
-      if (act && !isfinite(vnew)) atomicOr(&p.flags[FLAG_NONFINITE], 1);
-    }
+    // the substitution: x = u - w x_parent, v += x; the accumulators return to zero
     for (int k = 1; k < KN; ++k) {
       const int64_t i = nb + 64 * (int64_t)k;
-      const double x = Rw[i] - Dw[i] * Rw[nb + 64 * (int64_t)p.nidx[i].par];
-      Rw[i] = x;
+      const double x = Rw[i] - Dw[i] * DVw[nb + 64 * (int64_t)p.nidx[i].par];
+      DVw[i] = x;
       V[i] += x;
+      Dw[i] = 0.0;
+      Rw[i] = 0.0;
     }
     const bool spk = act && vold < theta && theta <= vnew;
     const uint64_t mask = __ballot(spk);
