@@ -1,19 +1,13 @@
 """The cell-group autotuner (cn_autotune): it times candidate shapes on the model itself, caches its choice by the
 model's signature, and the shape it picks changes the grouping only: every shape gives the default shape's results
 bitwise (the arithmetic of a compartment does not depend on the group it sits in)."""
-import sys
-
 import numpy as np
 import pytest
 
 from paper_1901_10975_amd import synth
+from tests.progress import say
 
 pytestmark = pytest.mark.gpu
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def _engine(m, **kw):

@@ -5,20 +5,14 @@
 * A failure during the graph capture must end the capture: the caller's stream is usable afterwards.
 * A non-finite membrane potential (a current far beyond any physiological value) is reported as CN_E_NUMERIC.
 """
-import sys
-
 import numpy as np
 import pytest
 
 from paper_1901_10975_amd import synth
 from tests import models as TM
+from tests.progress import say
 
 pytestmark = pytest.mark.gpu
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def test_failure_after_queued_work_breaks_the_model():

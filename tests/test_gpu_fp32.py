@@ -1,20 +1,14 @@
 """FP32-mechanism path (reading R12) against the FP64 oracle: every spike of the oracle is matched by the same cell's
 spike of the same rank at most one step away (and no extra spikes), and the voltage deviation is bounded. The
 deviations measured here are the figures stated for each config."""
-import sys
-
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_1901_10975_amd import synth
+from tests.progress import say
 
 pytestmark = pytest.mark.gpu
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def _run(m, checkpoints, cells=None, **kw):

@@ -2,23 +2,17 @@
 coupled cable system) on the GPU against the oracle, on both layouts: identical spike (gid, step) lists and FP64
 voltages within max(1e-10, 10 s(t)); zero-conductance junctions leave every result bitwise unchanged; a split run
 equals the uninterrupted one bitwise; the FP32-mechanism path keeps every spike within one step of the oracle."""
-import sys
-
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_1901_10975_amd import synth
 from tests.test_gpu_parity import assert_spikes_equal, lockstep
+from tests.progress import say
 
 pytestmark = pytest.mark.gpu
 
 LAYOUTS = ["level", "interleaved"]
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def _ring(g=0.05, cluster=3, per_pair=2, n_cells=300, n_comp=200):

@@ -2,23 +2,17 @@
 oracle, with the parity bars of the level layout: identical spike (gid, step) lists and FP64 voltages within
 max(1e-10, 10 s(t)); a split run equals the uninterrupted one bitwise; the FP32-mechanism path keeps every spike
 within one step of the FP64 oracle."""
-import sys
-
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_1901_10975_amd import synth
 from tests.test_gpu_parity import _edge_model, assert_spikes_equal, lockstep
+from tests.progress import say
 
 pytestmark = pytest.mark.gpu
 
 IL = dict(layout="interleaved")
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def test_clamped_cells_interleaved():

@@ -2,19 +2,13 @@
 into K partitions, each a model of its own on the device whose remote inputs arrive as kicks at step k + D, give
 bitwise the voltages and spikes of the single device run. This is what each GPU of a multi-GPU run computes between
 exchanges; the exchange itself (an all-gather of the interval's spike records) is not built here."""
-import sys
-
 import numpy as np
 import pytest
 
 from tests.test_oracle_pins import _partitioned_run, _small_ring
+from tests.progress import say
 
 pytestmark = pytest.mark.gpu
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 class _Device:

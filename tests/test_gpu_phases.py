@@ -7,6 +7,8 @@ import sys
 
 import pytest
 
+from tests.progress import say
+
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -15,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_phase_clocks_cover_every_phase():
     from paper_1901_10975_amd import build as B, cn
     assert os.path.exists(B.LIB_PHASE), "build the profiling library first"
-    print("phase clocks: cortex_50k recipe, 2000 cells, 3 intervals", flush=True)
+    say("phase clocks: cortex_50k recipe, 2000 cells, 3 intervals")
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--phase-clocks", "--n-cells", "2000",
                         "--steps", "3", "--warmup", "1"], capture_output=True, text=True, timeout=300, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-3000:]
@@ -26,4 +28,4 @@ def test_phase_clocks_cover_every_phase():
         assert set(share) == set(cn.PHASES)
         assert all(v > 0.0 for v in share.values()), share
         assert abs(sum(share.values()) - 1.0) < 1e-9
-        print(prec, {k: round(v, 3) for k, v in share.items()}, flush=True)
+        say(prec, {k: round(v, 3) for k, v in share.items()})

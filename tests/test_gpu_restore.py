@@ -4,22 +4,16 @@ background key follows the oracle restarted the same way.
 
 A checkpoint is the readouts at step s (cn_voltages, cn_mech_state of every state, cn_spikes); cn_restore writes them
 into a model that has not run and queues again every NetCon event of the listed spikes due at or after s."""
-import sys
-
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_1901_10975_amd import synth
+from tests.progress import say
 
 pytestmark = pytest.mark.gpu
 
 THREADS = 16
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def _engine(m, **kw):

@@ -1,21 +1,15 @@
 """cn_mech_state_noalloc, the state readout for callers that cannot allocate device memory, against cn_mech_state:
 bitwise the same values on two calls in a row (the second on a smaller input), in both precisions, for every
 state of every mechanism; requests beyond the static buffer are refused."""
-import sys
-
 import numpy as np
 import pytest
 
 from paper_1901_10975_amd import synth
+from tests.progress import say
 
 pytestmark = pytest.mark.gpu
 
 STATES = (("hh", 0), ("hh", 1), ("hh", 2), ("km", 0), ("cahi", 0), ("cahi", 1), ("expsyn", 0))
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mech"])
